@@ -1,0 +1,200 @@
+/*
+ * qmg -- shifted solves (Q - tau I) x = b for the Hermitian Wilson(-clover)
+ * Dirac operator Q = Gamma5 D on one MI355X (gfx950).
+ *
+ * The operation is the inner solve of the GD-lambda-AMG eigensolver of
+ * Frommer, Kahl, Knechtli, Rottmann, Strebel, Zwaan (arXiv:2004.08146):
+ * the correction equation (eq. (1.1) / eq. (3.3)), solved in its
+ * Gamma5-preconditioned form (D - tau Gamma5) x = Gamma5 b (eq. (3.6) <=> eq. (3.7)) by
+ * FGMRES with a two-level aggregation multigrid preconditioner (Sec. 2)
+ * whose smoother is red-black SAP (Sec. 2, eq. (2.10)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice dims[4] = {N0 (time), N1, N2, N3}; canonical site index
+ * ((x0*N1 + x1)*N2 + x2)*N3 + x3; periodic in all directions.
+ * Canonical spinor: complex128 [V][4 spin][3 colour] (interleaved re, im).
+ * Canonical gauge field: complex128 [V][4 mu][3][3]; U[x][mu] multiplies
+ * psi(x + mu) in the forward hop of eq. (2.5).
+ * Gamma basis: chiral, gamma5 = diag(1, 1, -1, -1) (Sec. 2);
+ * gamma0 = [[0,-I],[-I,0]], gamma_k = [[0,-i sigma_k],[i sigma_k,0]].
+ *
+ * Internal ("packed") fields live on the device in a block-major layout
+ * private to the library: produce them with qmg_pack, read them back with
+ * qmg_unpack; qmg_field_bytes gives the size of one field.  nrhs fields are
+ * stored back to back.  Precisions: QMG_F64 (double), QMG_F32 (float),
+ * QMG_BF16 (bfloat16 storage, float arithmetic).
+ * Coarse vectors (restrict / prolong / apply_coarse) are complex
+ * [nrhs][nblocks][2*ntv] in double for QMG_F64 and float otherwise, coarse
+ * site order as reported by qmg_coarse_site_order.
+ *
+ * Ownership: every pointer argument is owned by the caller; unless stated
+ * otherwise pointers to fields are DEVICE pointers on the context's device
+ * and tau arrays are HOST pointers.  The library copies what it keeps
+ * (gauge field, clover term, interpolation, coarse operator) and holds no
+ * caller pointer after a call returns.  Workspace is allocated lazily and
+ * released by qmg_destroy.
+ *
+ * Asynchrony: compute calls enqueue on `stream` and return without waiting,
+ * except qmg_set_gauge, qmg_set_test_vectors, qmg_setup_mg, qmg_field_dot,
+ * qmg_coarse_solve, qmg_vcycle, qmg_solve_shifted and qmg_autotune, which
+ * synchronise the stream.
+ *
+ * Errors: the return code is the only channel (no C++ exception crosses the
+ * interface); qmg_last_error gives a message.  A context is not thread safe.
+ */
+#ifndef QMG_H
+#define QMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qmg_ctx qmg_ctx;
+
+typedef enum {
+  QMG_OK = 0,
+  QMG_NOT_CONVERGED = 1, /* warning: outputs are valid, tolerance not reached */
+  QMG_E_ARG = -1,        /* invalid argument (sizes, pointers, blocking) */
+  QMG_E_STATE = -2,      /* call needs state not set yet (gauge, multigrid) */
+  QMG_E_NOMEM = -3,      /* device allocation failed */
+  QMG_E_HIP = -4,        /* HIP runtime error */
+  QMG_E_NUMERIC = -5     /* NaN/Inf or breakdown detected */
+} qmg_status;
+
+typedef enum { QMG_F64 = 0, QMG_F32 = 1, QMG_BF16 = 2 } qmg_prec;
+
+/* Solver parameters (defaults from the paper's parameter table and readings:
+ * qmg_default_params). */
+typedef struct {
+  double tol;          /* stop at ||b - (Q - tau) x|| / ||b|| <= tol (1e-10) */
+  int maxiter;         /* max FGMRES iterations (preconditioner applications) */
+  int restart;         /* FGMRES restart length m */
+  int nu_post;         /* SAP sweeps after the coarse correction (3) */
+  int n_mr;            /* minimal-residual steps per SAP block solve (3) */
+  int coarse_maxiter;  /* max coarse GMRES iterations per V-cycle */
+  double coarse_tol;   /* coarse residual reduction (0.5); <= 0: run coarse_maxiter */
+  qmg_prec mg_prec;    /* precision of the V-cycle (SAP, transfer, coarse) */
+  int use_coarse;      /* 1: two-level V-cycle; 0: SAP only (no coarse level) */
+  int use_graph;       /* 1: replay the V-cycle as a captured HIP graph */
+} qmg_params;
+
+typedef struct {
+  int iters;           /* FGMRES iterations for this right-hand side */
+  int restarts;        /* restart cycles */
+  int coarse_iters;    /* total coarse GMRES iterations */
+  double true_relres;  /* final ||b - (Q - tau) x|| / ||b||, FP64 */
+  double seconds;      /* wall time of the whole batched solve */
+} qmg_stats;
+
+qmg_params qmg_default_params(void);
+
+/* Create a context for lattice dims with Schwarz/aggregation blocks `block`
+ * (each extent a power of two dividing the lattice; at most 1024 sites per
+ * block) on HIP device `device`.  SAP and multigrid additionally need 16..256
+ * sites per block and an even number (>= 2) of blocks per direction
+ * (red-black colouring of the blocks, Sec. 2, text after eq. (2.10));
+ * apply-only contexts may use a single block per direction.
+ * Returns QMG_E_ARG for invalid shapes, QMG_E_HIP if the device is unusable. */
+qmg_status qmg_create(qmg_ctx** ctx, const int dims[4], const int block[4], int device);
+qmg_status qmg_destroy(qmg_ctx* ctx);
+const char* qmg_last_error(const qmg_ctx* ctx);
+
+/* Bytes of one internal spinor field / one coarse vector in precision p. */
+size_t qmg_field_bytes(const qmg_ctx* ctx, qmg_prec p);
+size_t qmg_coarse_bytes(const qmg_ctx* ctx, qmg_prec p);
+/* Lexicographic block index (((X0*NB1+X1)*NB2+X2)*NB3+X3) of every coarse
+ * site in library order; out is a HOST array of nblocks entries. */
+qmg_status qmg_coarse_site_order(const qmg_ctx* ctx, int64_t* out, int64_t n);
+
+/* Canonical complex128 spinors (device) <-> internal fields of precision p
+ * (RNE conversion when narrowing). */
+qmg_status qmg_pack(qmg_ctx* ctx, void* dev_internal, const double* canon, int nrhs,
+                    qmg_prec p, hipStream_t stream);
+qmg_status qmg_unpack(qmg_ctx* ctx, double* canon, const void* dev_internal, int nrhs,
+                      qmg_prec p, hipStream_t stream);
+
+/* result[2k], result[2k+1] = Re, Im of <a_k, b_k> = sum conj(a_k) b_k over one
+ * field (fixed summation order, accumulated in double); result is a HOST
+ * array of 2*nrhs doubles; synchronises the stream. */
+qmg_status qmg_field_dot(qmg_ctx* ctx, double* result, const void* a, const void* b, int nrhs, qmg_prec p,
+                         hipStream_t stream);
+
+/* Gauge field (device, canonical complex128), bare mass m0 of eq. (2.5) and
+ * clover coefficient csw.  Builds the clover term on the device (clover-leaf
+ * field strength, traceless) and keeps F64/F32/BF16 copies.  Invalidates the
+ * multigrid hierarchy. */
+qmg_status qmg_set_gauge(qmg_ctx* ctx, const double* U_canon, double m0, double csw,
+                         hipStream_t stream);
+
+/* out_k = Q in_k = Gamma5 D in_k (eq. (2.5), Q = Gamma5 D). */
+qmg_status qmg_apply_Q(qmg_ctx* ctx, void* out, const void* in, int nrhs, qmg_prec p,
+                       hipStream_t stream);
+/* out_k = (Q - tau_k I) in_k (eq. (1.1)); tau: host array of nrhs shifts. */
+qmg_status qmg_apply_Q_shifted(qmg_ctx* ctx, void* out, const void* in, const double* tau,
+                               int nrhs, qmg_prec p, hipStream_t stream);
+/* out_k = (D - tau_k Gamma5) in_k, the Gamma5-preconditioned operator (eq. (3.7)). */
+qmg_status qmg_apply_A(qmg_ctx* ctx, void* out, const void* in, const double* tau,
+                       int nrhs, qmg_prec p, hipStream_t stream);
+
+/* nsweep red-black SAP sweeps (Sec. 2) on (D - tau_k Gamma5) x_k = f_k,
+ * updating x in place; each block solve is n_mr minimal-residual steps from
+ * zero on the block-restricted operator; colour-0 blocks first. */
+qmg_status qmg_sap_smooth(qmg_ctx* ctx, void* x, const void* f, const double* tau, int nrhs,
+                          int nsweep, int n_mr, qmg_prec p, hipStream_t stream);
+
+/* Build the interpolation P from ntv test vectors W (internal F64 fields):
+ * per aggregate (block x chirality half) the restrictions of W are
+ * orthonormalised (modified Gram-Schmidt twice, column order), then the
+ * Galerkin coarse operator D_c = P^H D P (Sec. 2) is assembled.
+ * Returns QMG_E_NUMERIC for locally rank-deficient W. */
+qmg_status qmg_set_test_vectors(qmg_ctx* ctx, const void* W, int ntv, hipStream_t stream);
+/* Adaptive setup (reading of the paper's setup parameters): smooth W0 with
+ * `smooth` SAP sweeps on D w = 0, then setup_iters-1 rounds of V-cycle
+ * inverse iteration at tau = 0, rebuilding P and D_c each round.  W0 is
+ * overwritten with the final test vectors (internal F64). */
+qmg_status qmg_setup_mg(qmg_ctx* ctx, void* W0, int ntv, int setup_iters, int smooth,
+                        int n_mr, int coarse_maxiter, double coarse_tol, hipStream_t stream);
+
+/* y_k = P^H v_k and v_k = P y_k (Sec. 2, R = P^H). */
+qmg_status qmg_restrict(qmg_ctx* ctx, void* yc, const void* v, int nrhs, qmg_prec p,
+                        hipStream_t stream);
+qmg_status qmg_prolong(qmg_ctx* ctx, void* v, const void* yc, int nrhs, qmg_prec p,
+                       hipStream_t stream);
+/* out_k = (D_c - tau_k Gamma5^c) in_k, Gamma5^c = diag(+I_ntv, -I_ntv) per coarse site. */
+qmg_status qmg_apply_coarse(qmg_ctx* ctx, void* out, const void* in, const double* tau,
+                            int nrhs, qmg_prec p, hipStream_t stream);
+/* Coarse GMRES from zero on (D_c - tau_k Gamma5^c) y_k = r_k, for exactly
+ * `iters` steps when tol <= 0, else until ||res|| <= tol ||r_k||. */
+qmg_status qmg_coarse_solve(qmg_ctx* ctx, void* y, const void* r, const double* tau, int nrhs,
+                            int iters, double tol, qmg_prec p, hipStream_t stream);
+/* One V-cycle z_k = M r_k (no pre-smoothing, coarse solve, nu_post SAP sweeps). */
+qmg_status qmg_vcycle(qmg_ctx* ctx, void* z, const void* r, const double* tau, int nrhs,
+                      const qmg_params* params, hipStream_t stream);
+
+/* Solve (Q - tau_k I) x_k = b_k for k < nrhs (internal F64 fields x, b) by
+ * FGMRES on (D - tau_k Gamma5) x_k = Gamma5 b_k, x0 = 0, each right-hand side
+ * with its own Krylov space; stats: host array of nrhs (may be NULL).
+ * Returns QMG_NOT_CONVERGED if some column missed tol within maxiter. */
+qmg_status qmg_solve_shifted(qmg_ctx* ctx, void* x, const void* b, const double* tau, int nrhs,
+                             const qmg_params* params, qmg_stats* stats, hipStream_t stream);
+
+/* Gauge force of L = phi^H Q x (Wilson part; QMG_E_STATE when csw != 0):
+ * dU[x][mu][a][b] = dL/dU_mu(x)_ab and dUbar = dL/d conj(U_mu(x)_ab), both
+ * canonical complex128 device arrays; phi, x internal F64 fields. */
+qmg_status qmg_gauge_force(qmg_ctx* ctx, double* dU, double* dUbar, const void* phi,
+                           const void* x, hipStream_t stream);
+
+/* Time the launch variants of the hot kernels for this context's shape and
+ * pick the fastest; results are cached in a JSON file keyed by device
+ * architecture and lattice shape (path may be NULL: no file). */
+qmg_status qmg_autotune(qmg_ctx* ctx, const char* cache_json_path);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QMG_H */

@@ -2,7 +2,7 @@
 
 A block is a B0 x B1 x B2 x B3 sub-lattice; block coordinates are
 X_mu = floor(x_mu / B_mu) and the colour of a block is (sum_mu X_mu) mod 2
-(red-black ordering of the Schwarz domains, Sec. 2, text after the SAP error
+(red-black ordering of the Schwarz domains, Sec. 2, text after eq. (2.10), the SAP error
 propagator).  Blocks are numbered lexicographically,
 b = ((X0*NB1 + X1)*NB2 + X2)*NB3 + X3, and sites inside a block likewise.
 """

@@ -1,7 +1,7 @@
 """Dense matrix of D assembled entry block by entry block (small lattices).
 
 Independent of the matrix-free ``oracle.dirac`` code: it writes out the
-site couplings of eq. (2.5),
+site couplings of eq. (2.6),
 
   D_{x, x+mu} = -1/2 (I - gamma_mu) (x) U_mu(x),
   D_{x, x-mu} = -1/2 (I + gamma_mu) (x) U_mu(x - mu)^H,

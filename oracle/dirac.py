@@ -1,6 +1,6 @@
 """Wilson(-clover) Dirac operator D, Q = Gamma5 D and the shifted forms.
 
-Follows eq. (2.4) (the action of D on a quark field) with lattice spacing
+Follows eq. (2.5) (the action of D on a quark field) with lattice spacing
 a = 1 and periodic boundaries in all four directions:
 
   (D psi)(x) = (m0 + 4) psi(x) + C(x) psi(x)
@@ -8,9 +8,9 @@ a = 1 and periodic boundaries in all four directions:
                - 1/2 sum_mu ((I + gamma_mu) (x) U_mu(x - mu)^H) psi(x - mu),
 
 C(x) the optional clover term (``oracle.clover``).  Q = Gamma5 D is the
-Hermitian Wilson-Dirac operator (Sec. 2, definition after eq. (2.6));
+Hermitian Wilson-Dirac operator (Sec. 2, definition after eq. (2.7));
 the shifted system of eq. (1.1) is (Q - tau I) x = b, and its
-Gamma5-preconditioned form, eq. (3.3), is (D - tau Gamma5) x = Gamma5 b.
+Gamma5-preconditioned form, eq. (3.6) <=> eq. (3.7), is (D - tau Gamma5) x = Gamma5 b.
 
 Fields are complex128 arrays ``psi[N0, N1, N2, N3, 4, 3]`` and
 ``U[N0, N1, N2, N3, 4, 3, 3]`` (see ``synth.fields``).
@@ -67,7 +67,7 @@ def site_diag(psi, m0, clover=None):
 
 
 def apply_D(U, psi, m0, clover=None):
-    """D psi per eq. (2.4) (plus the clover term when given)."""
+    """D psi per eq. (2.5) (plus the clover term when given)."""
     out = site_diag(psi, m0, clover)
     for mu in range(4):
         out = out + hop_forward(U, psi, mu) + hop_backward(U, psi, mu)
@@ -85,12 +85,12 @@ def apply_Q(U, psi, m0, clover=None):
 
 
 def apply_Q_shifted(U, psi, m0, tau, clover=None):
-    """(Q - tau I) psi, the operator of eq. (1.1) / eq. (3.2)."""
+    """(Q - tau I) psi, the operator of eq. (1.1) / eq. (3.6)."""
     return apply_Q(U, psi, m0, clover) - tau * psi
 
 
 def apply_A(U, psi, m0, tau, clover=None):
-    """(D - tau Gamma5) psi, the Gamma5-preconditioned operator of eq. (3.3)."""
+    """(D - tau Gamma5) psi, the Gamma5-preconditioned operator of eq. (3.7)."""
     return apply_D(U, psi, m0, clover) - tau * gamma5(psi)
 
 

@@ -1,6 +1,6 @@
 """Gauge-field derivative of L = phi^H Q x (Wilson part).
 
-Not part of the paper; follows from eq. (2.4).  L contains each link U_mu(y)
+Not part of the paper; follows from eq. (2.5).  L contains each link U_mu(y)
 linearly through the forward hop at y and its conjugate through the backward
 hop at y + mu, so the two Wirtinger derivatives per link are
 

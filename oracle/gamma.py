@@ -1,7 +1,7 @@
 """Euclidean gamma matrices in a chiral basis with gamma5 = diag(I2, -I2).
 
 The paper fixes only gamma5 = gamma0 gamma1 gamma2 gamma3 = diag(I2, -I2)
-(Sec. 2, text before eq. (2.5)) and the Clifford relation
+(Sec. 2, text before eq. (2.5), the Wilson-Dirac operator) and the Clifford relation
 gamma_mu gamma_nu + gamma_nu gamma_mu = 2 delta_mu_nu (eq. (2.3)).  The
 basis chosen here (reading: gamma0 = [[0,-I],[-I,0]],
 gamma_k = [[0,-i sigma_k],[i sigma_k,0]]) satisfies both; any such basis gives

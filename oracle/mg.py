@@ -1,10 +1,10 @@
 """Two-level aggregation multigrid pieces: P, R = P^H, D_c = P^H D P, V-cycle.
 
-Sec. 2: E_2g = (I - M A)^nu (I - P A_c^{-1} R A)(I - M A)^mu with R = P^H and
+eq. (2.8): E_2g = (I - M A)^nu (I - P A_c^{-1} R A)(I - M A)^mu with R = P^H and
 the Galerkin coarse operator D_c = P^H D P; P is block diagonal with one block
 per aggregate, built from test vectors W (Sec. 3.1, local-coherence paragraph
 and the figure on the construction of P).  Spin structure is kept
-(Gamma5 P = P Gamma5^c, eq. (2.7)) by splitting every lattice block into two
+(Gamma5 P = P Gamma5^c, text before eq. (2.9)) by splitting every lattice block into two
 aggregates: spins {0,1} (gamma5 = +1) and spins {2,3} (gamma5 = -1).
 
 Readings where the paper is silent:

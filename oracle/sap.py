@@ -1,10 +1,10 @@
 """Red-black Schwarz alternating procedure (SAP) with minimal-residual block solves.
 
-Sec. 2: one SAP step multiplies the block corrections
+eq. (2.10): one SAP step multiplies the block corrections
 I - I_i A_i^{-1} I_i^H A over all blocks i, A_i = I_i^H A I_i the restriction
 of the operator to block i (hops that leave the block are dropped); blocks of
 one colour are independent and are treated together.  The operator here is
-the Gamma5-preconditioned A_tau = D - tau Gamma5 of eq. (3.3).
+the Gamma5-preconditioned A_tau = D - tau Gamma5 of eq. (3.7).
 
 Readings where the paper leaves the details open:
 * block solves are n_mr steps of the minimal-residual method (GMRES(1))

@@ -1,6 +1,6 @@
 """The shifted solve (Q - tau I) x = b in its Gamma5-preconditioned form.
 
-eq. (3.2) -> eq. (3.3): (Q - tau I) x = b  <=>  (D - tau Gamma5) x = Gamma5 b,
+eq. (3.6) <=> eq. (3.7): (Q - tau I) x = b  <=>  (D - tau Gamma5) x = Gamma5 b,
 solved with FGMRES (Sec. 2, multigrid as a preconditioner of a flexible Krylov
 method) preconditioned by the two-level V-cycle, or by SAP alone when no
 coarse level is given (the coarse-correction-off variant of Sec. 4).

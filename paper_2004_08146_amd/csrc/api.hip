@@ -1,0 +1,446 @@
+// The C interface: context, validation, error reporting and dispatch to the
+// kernel launchers and solver drivers.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qmg_ctx.h"
+
+qmg_status set_err(qmg_ctx* c, qmg_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+qmg_status hip_err(qmg_ctx* c, hipError_t e, const char* where) {
+  if (e == hipErrorOutOfMemory) return set_err(c, QMG_E_NOMEM, std::string(where) + ": out of device memory");
+  return set_err(c, QMG_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t field_elems(const qmg_ctx* c) { return (size_t)c->g.V * 12; }
+size_t coarse_elems(const qmg_ctx* c) { return (size_t)c->g.nb * 2 * c->ntv; }
+
+void* ws_get(qmg_ctx* c, const std::string& name, size_t bytes) {
+  auto it = c->ws.find(name);
+  if (it != c->ws.end() && it->second.second >= bytes) return it->second.first;
+  if (it != c->ws.end()) {
+    hipDeviceSynchronize();
+    hipFree(it->second.first);
+    c->ws.erase(it);
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+  c->ws[name] = {p, bytes};
+  return p;
+}
+
+void ws_release(qmg_ctx* c, const std::string& name) {
+  auto it = c->ws.find(name);
+  if (it == c->ws.end()) return;
+  hipDeviceSynchronize();
+  hipFree(it->second.first);
+  c->ws.erase(it);
+}
+
+namespace {
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2(int x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return r;
+}
+
+qmg_status check_prec(qmg_ctx* c, int p) {
+  if (p != QMG_F64 && p != QMG_F32 && p != QMG_BF16) return set_err(c, QMG_E_ARG, "unknown precision");
+  return QMG_OK;
+}
+qmg_status check_nrhs(qmg_ctx* c, int nrhs) {
+  if (nrhs < 1 || nrhs > QMG_MAXRHS) return set_err(c, QMG_E_ARG, "nrhs must be in 1..64");
+  return QMG_OK;
+}
+qmg_status need_gauge(qmg_ctx* c) {
+  if (!c->have_gauge) return set_err(c, QMG_E_STATE, "qmg_set_gauge has not been called");
+  return QMG_OK;
+}
+qmg_status need_sap(qmg_ctx* c) {
+  if (!c->sap_ok)
+    return set_err(c, QMG_E_ARG,
+                   "SAP and multigrid need an even number (>= 2) of blocks per direction and 16..256 sites per block");
+  return QMG_OK;
+}
+qmg_status need_mg(qmg_ctx* c) {
+  if (!c->have_mg) return set_err(c, QMG_E_STATE, "qmg_set_test_vectors / qmg_setup_mg has not been called");
+  return QMG_OK;
+}
+qmg_status check_tau(qmg_ctx* c, const double* tau, int nrhs) {
+  if (!tau) return set_err(c, QMG_E_ARG, "tau is NULL");
+  for (int k = 0; k < nrhs; ++k)
+    if (!std::isfinite(tau[k])) return set_err(c, QMG_E_ARG, "tau must be finite");
+  return QMG_OK;
+}
+
+#define QMG_TRY(x)                  \
+  do {                              \
+    qmg_status _s = (x);            \
+    if (_s != QMG_OK) return _s;    \
+  } while (0)
+
+qmg_status hipchk(qmg_ctx* c, hipError_t e, const char* where) {
+  return e == hipSuccess ? QMG_OK : hip_err(c, e, where);
+}
+
+void free_ptr(void*& p) {
+  if (p) hipFree(p);
+  p = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+qmg_params qmg_default_params(void) {
+  qmg_params p;
+  p.tol = 1e-10;
+  p.maxiter = 1000;
+  p.restart = 16;
+  p.nu_post = 3;
+  p.n_mr = 3;
+  p.coarse_maxiter = 50;
+  p.coarse_tol = 0.5;
+  p.mg_prec = QMG_F64;
+  p.use_coarse = 1;
+  p.use_graph = 0;
+  return p;
+}
+
+qmg_status qmg_create(qmg_ctx** out, const int dims[4], const int block[4], int device) {
+  if (!out || !dims || !block) return QMG_E_ARG;
+  *out = nullptr;
+  qmg_ctx* c = new qmg_ctx();
+  c->device = device;
+  Geom& g = c->g;
+  int64_t V = 1;
+  int nb = 1, bs = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (dims[mu] < 1 || !is_pow2(block[mu]) || dims[mu] % block[mu]) {
+      delete c;
+      return QMG_E_ARG;
+    }
+    g.dims[mu] = dims[mu];
+    g.block[mu] = block[mu];
+    g.nbk[mu] = dims[mu] / block[mu];
+    g.msk[mu] = block[mu] - 1;
+    V *= dims[mu];
+    nb *= g.nbk[mu];
+    bs *= block[mu];
+  }
+  if (bs > 1024 || V > (int64_t)1 << 31 || (int64_t)nb * 36 * bs * 16 > ((int64_t)1 << 40)) {
+    delete c;
+    return QMG_E_ARG;
+  }
+  g.sh[3] = 0;
+  g.sh[2] = ilog2(block[3]);
+  g.sh[1] = g.sh[2] + ilog2(block[2]);
+  g.sh[0] = g.sh[1] + ilog2(block[1]);
+  g.bs_log = ilog2(bs);
+  g.nb = nb;
+  g.V = V;
+  c->sap_ok = bs <= 256 && bs >= 16;
+  for (int mu = 0; mu < 4; ++mu) c->sap_ok = c->sap_ok && g.nbk[mu] >= 2 && g.nbk[mu] % 2 == 0;
+  // colour-major block numbering
+  std::vector<int> id_of_lex(nb);
+  c->lex_of_block.assign(nb, 0);
+  int next = 0;
+  for (int col = 0; col < 2; ++col)
+    for (int lex = 0; lex < nb; ++lex) {
+      int r = lex, X[4], sum = 0;
+      for (int mu = 3; mu >= 0; --mu) { X[mu] = r % g.nbk[mu]; r /= g.nbk[mu]; sum += X[mu]; }
+      if (sum % 2 != col) continue;
+      id_of_lex[lex] = next;
+      c->lex_of_block[next] = lex;
+      ++next;
+    }
+  g.ncol0 = 0;
+  c->h_bcoord.assign((size_t)nb * 4, 0);
+  c->h_nbr.assign((size_t)nb * 8, 0);
+  for (int b = 0; b < nb; ++b) {
+    int r = (int)c->lex_of_block[b], X[4], sum = 0;
+    for (int mu = 3; mu >= 0; --mu) { X[mu] = r % g.nbk[mu]; r /= g.nbk[mu]; sum += X[mu]; }
+    if (sum % 2 == 0) ++g.ncol0;
+    for (int mu = 0; mu < 4; ++mu) c->h_bcoord[b * 4 + mu] = X[mu];
+    for (int mu = 0; mu < 4; ++mu)
+      for (int dir = 0; dir < 2; ++dir) {
+        int Y[4] = {X[0], X[1], X[2], X[3]};
+        Y[mu] = (Y[mu] + (dir == 0 ? 1 : g.nbk[mu] - 1)) % g.nbk[mu];
+        int lex = ((Y[0] * g.nbk[1] + Y[1]) * g.nbk[2] + Y[2]) * g.nbk[3] + Y[3];
+        c->h_nbr[b * 8 + 2 * mu + dir] = id_of_lex[lex];
+      }
+  }
+  if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->d_nbr, sizeof(int) * nb * 8) != hipSuccess ||
+      hipMalloc(&c->d_bcoord, sizeof(int) * nb * 4) != hipSuccess ||
+      hipMemcpy(c->d_nbr, c->h_nbr.data(), sizeof(int) * nb * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_bcoord, c->h_bcoord.data(), sizeof(int) * nb * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    qmg_destroy(c);
+    return QMG_E_HIP;
+  }
+  g.nbr = c->d_nbr;
+  g.bcoord = c->d_bcoord;
+  *out = c;
+  return QMG_OK;
+}
+
+qmg_status qmg_destroy(qmg_ctx* c) {
+  if (!c) return QMG_OK;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  if (c->graph) hipGraphExecDestroy(c->graph);
+  for (int p = 0; p < 3; ++p) {
+    free_ptr(c->U[p]);
+    free_ptr(c->Dg[p]);
+  }
+  for (auto& kv : c->ws) hipFree(kv.second.first);
+  if (c->d_nbr) hipFree(c->d_nbr);
+  if (c->d_bcoord) hipFree(c->d_bcoord);
+  delete c;
+  return QMG_OK;
+}
+
+const char* qmg_last_error(const qmg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+size_t qmg_field_bytes(const qmg_ctx* c, qmg_prec p) { return c ? field_elems(c) * cbytes(p) : 0; }
+
+size_t qmg_coarse_bytes(const qmg_ctx* c, qmg_prec p) {
+  return c ? (size_t)c->g.nb * 2 * c->ntv * cbytes(coarse_prec(p)) : 0;
+}
+
+qmg_status qmg_coarse_site_order(const qmg_ctx* c, int64_t* out, int64_t n) {
+  if (!c || !out || n < c->g.nb) return QMG_E_ARG;
+  for (int b = 0; b < c->g.nb; ++b) out[b] = c->lex_of_block[b];
+  return QMG_OK;
+}
+
+qmg_status qmg_pack(qmg_ctx* c, void* dev, const double* canon, int nrhs, qmg_prec p, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  if (!dev || !canon || nrhs < 1) return set_err(c, QMG_E_ARG, "pack: bad arguments");
+  hipSetDevice(c->device);
+  return hipchk(c, launch_pack(c->g, dev, p, canon, nrhs, s), "pack");
+}
+
+qmg_status qmg_unpack(qmg_ctx* c, double* canon, const void* dev, int nrhs, qmg_prec p, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  if (!dev || !canon || nrhs < 1) return set_err(c, QMG_E_ARG, "unpack: bad arguments");
+  hipSetDevice(c->device);
+  return hipchk(c, launch_unpack(c->g, canon, dev, p, nrhs, s), "unpack");
+}
+
+qmg_status qmg_field_dot(qmg_ctx* c, double* result, const void* a, const void* b, int nrhs, qmg_prec p,
+                         hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  if (!result || !a || !b) return set_err(c, QMG_E_ARG, "field_dot: null pointer");
+  hipSetDevice(c->device);
+  const int64_t n = (int64_t)field_elems(c);
+  double* d = (double*)ws_get(c, "dot_out", sizeof(double) * 2 * nrhs);
+  double* part = (double*)ws_get(c, "dot_part", sizeof(double) * multidot_partial_doubles(n, 1, nrhs));
+  if (!d || !part) return set_err(c, QMG_E_NOMEM, "field_dot: out of device memory");
+  QMG_TRY(hipchk(c, launch_multidot(p, d, a, 0, 1, b, n, n, nrhs, part, s), "field_dot"));
+  QMG_TRY(hipchk(c, hipMemcpyAsync(result, d, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s), "field_dot D2H"));
+  return hipchk(c, hipStreamSynchronize(s), "field_dot sync");
+}
+
+qmg_status qmg_set_gauge(qmg_ctx* c, const double* U, double m0, double csw, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  if (!U || !std::isfinite(m0) || !std::isfinite(csw)) return set_err(c, QMG_E_ARG, "set_gauge: bad arguments");
+  hipSetDevice(c->device);
+  const size_t nel = (size_t)c->g.nb * 36 * ((size_t)1 << c->g.bs_log);
+  for (int p = 0; p < 3; ++p)
+    if (!c->U[p] && hipMalloc(&c->U[p], nel * cbytes(p)) != hipSuccess)
+      return set_err(c, QMG_E_NOMEM, "set_gauge: out of device memory");
+  QMG_TRY(hipchk(c, launch_pack_gauge(c->g, c->U[QMG_F64], U, s), "pack gauge"));
+  for (int p = 1; p < 3; ++p)
+    QMG_TRY(hipchk(c, launch_convert(c->U[p], p, c->U[QMG_F64], QMG_F64, (int64_t)nel, s), "convert gauge"));
+  c->clover = csw != 0.0;
+  if (c->clover) {
+    for (int p = 0; p < 3; ++p)
+      if (!c->Dg[p] && hipMalloc(&c->Dg[p], nel * cbytes(p)) != hipSuccess)
+        return set_err(c, QMG_E_NOMEM, "set_gauge: out of device memory");
+    QMG_TRY(hipchk(c, launch_clover(c->g, c->Dg[QMG_F64], c->U[QMG_F64], m0, csw, s), "clover"));
+    for (int p = 1; p < 3; ++p)
+      QMG_TRY(hipchk(c, launch_convert(c->Dg[p], p, c->Dg[QMG_F64], QMG_F64, (int64_t)nel, s), "convert clover"));
+  }
+  QMG_TRY(hipchk(c, hipStreamSynchronize(s), "set_gauge sync"));
+  c->m0 = m0;
+  c->csw = csw;
+  c->have_gauge = true;
+  c->have_mg = false;
+  return QMG_OK;
+}
+
+static qmg_status apply_common(qmg_ctx* c, void* out, const void* in, const double* tau, int nrhs, qmg_prec p,
+                               int mode, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_gauge(c));
+  if (!out || !in) return set_err(c, QMG_E_ARG, "apply: null field");
+  if (out == in) return set_err(c, QMG_E_ARG, "apply: out and in must not alias");
+  std::vector<double> t(nrhs, 0.0);
+  if (tau) {
+    QMG_TRY(check_tau(c, tau, nrhs));
+    for (int k = 0; k < nrhs; ++k) t[k] = tau[k];
+  }
+  hipSetDevice(c->device);
+  return hipchk(c, launch_dslash(c, p, out, in, t.data(), nrhs, mode, s), "apply");
+}
+
+qmg_status qmg_apply_Q(qmg_ctx* c, void* out, const void* in, int nrhs, qmg_prec p, hipStream_t s) {
+  return apply_common(c, out, in, nullptr, nrhs, p, 1, s);
+}
+
+qmg_status qmg_apply_Q_shifted(qmg_ctx* c, void* out, const void* in, const double* tau, int nrhs, qmg_prec p,
+                               hipStream_t s) {
+  if (c && !tau) return set_err(c, QMG_E_ARG, "tau is NULL");
+  return apply_common(c, out, in, tau, nrhs, p, 1, s);
+}
+
+qmg_status qmg_apply_A(qmg_ctx* c, void* out, const void* in, const double* tau, int nrhs, qmg_prec p,
+                       hipStream_t s) {
+  if (c && !tau) return set_err(c, QMG_E_ARG, "tau is NULL");
+  return apply_common(c, out, in, tau, nrhs, p, 0, s);
+}
+
+qmg_status qmg_sap_smooth(qmg_ctx* c, void* x, const void* f, const double* tau, int nrhs, int nsweep, int n_mr,
+                          qmg_prec p, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_gauge(c));
+  QMG_TRY(need_sap(c));
+  QMG_TRY(check_tau(c, tau, nrhs));
+  if (!x || !f || x == f || nsweep < 0 || n_mr < 0) return set_err(c, QMG_E_ARG, "sap_smooth: bad arguments");
+  hipSetDevice(c->device);
+  for (int sw = 0; sw < nsweep; ++sw)
+    for (int col = 0; col < 2; ++col)
+      QMG_TRY(hipchk(c, launch_sap_colour(c, p, x, f, tau, nrhs, col, n_mr, s), "sap"));
+  return QMG_OK;
+}
+
+qmg_status qmg_set_test_vectors(qmg_ctx* c, const void* W, int ntv, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(need_gauge(c));
+  QMG_TRY(need_sap(c));
+  if (!W || ntv < 1 || ntv > 32) return set_err(c, QMG_E_ARG, "set_test_vectors: need 1 <= ntv <= 32");
+  if (6 * ((int64_t)1 << c->g.bs_log) < ntv) return set_err(c, QMG_E_ARG, "ntv exceeds the aggregate size");
+  hipSetDevice(c->device);
+  return build_mg(c, W, ntv, s);
+}
+
+qmg_status qmg_setup_mg(qmg_ctx* c, void* W0, int ntv, int setup_iters, int smooth, int n_mr, int coarse_maxiter,
+                        double coarse_tol, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(need_gauge(c));
+  QMG_TRY(need_sap(c));
+  if (!W0 || ntv < 1 || ntv > 32 || setup_iters < 1 || smooth < 0 || n_mr < 0 || coarse_maxiter < 1)
+    return set_err(c, QMG_E_ARG, "setup_mg: bad arguments");
+  hipSetDevice(c->device);
+  return solver_setup(c, W0, ntv, setup_iters, smooth, n_mr, coarse_maxiter, coarse_tol, s);
+}
+
+qmg_status qmg_restrict(qmg_ctx* c, void* yc, const void* v, int nrhs, qmg_prec p, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_mg(c));
+  if (!yc || !v) return set_err(c, QMG_E_ARG, "restrict: null pointer");
+  hipSetDevice(c->device);
+  return hipchk(c, launch_restrict(c, p, yc, v, nrhs, s), "restrict");
+}
+
+qmg_status qmg_prolong(qmg_ctx* c, void* v, const void* yc, int nrhs, qmg_prec p, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_mg(c));
+  if (!yc || !v) return set_err(c, QMG_E_ARG, "prolong: null pointer");
+  hipSetDevice(c->device);
+  return hipchk(c, launch_prolong(c, p, v, yc, nrhs, s), "prolong");
+}
+
+qmg_status qmg_apply_coarse(qmg_ctx* c, void* out, const void* in, const double* tau, int nrhs, qmg_prec p,
+                            hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_mg(c));
+  QMG_TRY(check_tau(c, tau, nrhs));
+  if (!out || !in || out == in) return set_err(c, QMG_E_ARG, "apply_coarse: bad pointers");
+  hipSetDevice(c->device);
+  return hipchk(c, launch_coarse_apply(c, p, out, in, tau, nrhs, s), "apply_coarse");
+}
+
+qmg_status qmg_coarse_solve(qmg_ctx* c, void* y, const void* r, const double* tau, int nrhs, int iters, double tol,
+                            qmg_prec p, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_mg(c));
+  QMG_TRY(check_tau(c, tau, nrhs));
+  if (!y || !r || y == r || iters < 1) return set_err(c, QMG_E_ARG, "coarse_solve: bad arguments");
+  hipSetDevice(c->device);
+  return solver_coarse_gmres(c, p, y, r, tau, nrhs, iters, tol, nullptr, s);
+}
+
+qmg_status qmg_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
+                      hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_gauge(c));
+  QMG_TRY(need_sap(c));
+  QMG_TRY(check_tau(c, tau, nrhs));
+  if (!z || !r || z == r || !prm) return set_err(c, QMG_E_ARG, "vcycle: bad arguments");
+  QMG_TRY(check_prec(c, prm->mg_prec));
+  if (prm->use_coarse) QMG_TRY(need_mg(c));
+  hipSetDevice(c->device);
+  return solver_vcycle(c, z, r, tau, nrhs, prm, nullptr, s);
+}
+
+qmg_status qmg_solve_shifted(qmg_ctx* c, void* x, const void* b, const double* tau, int nrhs, const qmg_params* prm,
+                             qmg_stats* st, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_gauge(c));
+  QMG_TRY(need_sap(c));
+  QMG_TRY(check_tau(c, tau, nrhs));
+  if (!x || !b || x == b) return set_err(c, QMG_E_ARG, "solve_shifted: bad pointers");
+  qmg_params prm0 = prm ? *prm : qmg_default_params();
+  QMG_TRY(check_prec(c, prm0.mg_prec));
+  if (!(prm0.tol > 0) || prm0.maxiter < 1 || prm0.restart < 1 || prm0.nu_post < 0 || prm0.n_mr < 0 ||
+      prm0.coarse_maxiter < 1)
+    return set_err(c, QMG_E_ARG, "solve_shifted: bad parameters");
+  if (prm0.use_coarse) QMG_TRY(need_mg(c));
+  hipSetDevice(c->device);
+  return solver_fgmres(c, x, b, tau, nrhs, &prm0, st, s);
+}
+
+qmg_status qmg_gauge_force(qmg_ctx* c, double* dU, double* dUbar, const void* phi, const void* x, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(need_gauge(c));
+  if (c->clover) return set_err(c, QMG_E_STATE, "gauge_force: only the Wilson part (csw = 0) is implemented");
+  if (!dU || !dUbar || !phi || !x) return set_err(c, QMG_E_ARG, "gauge_force: null pointer");
+  hipSetDevice(c->device);
+  return hipchk(c, launch_force(c, dU, dUbar, phi, x, s), "gauge_force");
+}
+
+qmg_status qmg_autotune(qmg_ctx* c, const char* path) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(need_gauge(c));
+  hipSetDevice(c->device);
+  return tune_run(c, path);
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// Galerkin coarse operator D_c = P^H D P (Sec. 2) and its application
+// out_k = (D_c - tau_k Gamma5^c) in_k.
+//
+// D_c couples each coarse site (lattice block) b to itself and to its 8
+// neighbouring blocks.  It is assembled column by column: prolong a unit
+// coarse vector, split D applied to it into the block-local part (diagonal
+// plus hops inside the block) and the 8 hop parts that leave the block, and
+// restrict each part with the receiving block's P.  Blocks are stored
+// transposed, DcT[b][d][j][i] = D_c[b][d]_{ij}, d = 0 self, 1 + 2 mu for the
+// block at X + mu, 2 + 2 mu for X - mu (kept apart even when they coincide).
+#include "qmg_ctx.h"
+
+namespace {
+
+// out9[0] = block-local part, out9[1+2mu] / out9[2+2mu] = forward / backward
+// hop leaving the block (zero where the hop stays inside)
+__global__ __launch_bounds__(256) void k_split(Geom g, double2* out9, const double2* in, const double2* U,
+                                               const double2* diag, double mass4, int clover) {
+  int64_t site = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (site >= g.V) return;
+  const int b = (int)(site >> g.bs_log), l = (int)(site & ((1 << g.bs_log) - 1));
+  const int64_t fs = g.V * 12;
+  Spinor<double> self = load_spinor<double>(in, g, b, l);
+  Spinor<double> loc0;
+  if (clover) loc0 = apply_diag<double>(diag, g, b, l, self);
+  else
+    for (int s = 0; s < 4; ++s)
+      for (int c = 0; c < 3; ++c) loc0.s[s][c] = mass4 * self.s[s][c];
+  for (int mu = 0; mu < 4; ++mu) {
+    for (int dir = 0; dir < 2; ++dir) {
+      const bool fwd = dir == 0;
+      int bn, ln;
+      if (fwd) nb_fwd(g, b, l, mu, bn, ln);
+      else nb_bwd(g, b, l, mu, bn, ln);
+      Half<double> h = project(load_spinor<double>(in, g, bn, ln), mu, fwd);
+      Half<double> w = fwd ? umul(load_link<double>(U, g, b, mu, l), h)
+                           : udagmul(load_link<double>(U, g, bn, mu, ln), h);
+      Spinor<double> t;
+      for (int s = 0; s < 4; ++s)
+        for (int c = 0; c < 3; ++c) t.s[s][c] = czero<double>();
+      accum_recon(t, w, mu, fwd);
+      const bool inside = fwd ? (loc(g, l, mu) < g.msk[mu]) : (loc(g, l, mu) > 0);
+      Spinor<double> o;
+      for (int s = 0; s < 4; ++s)
+        for (int c = 0; c < 3; ++c) {
+          o.s[s][c] = inside ? czero<double>() : (-0.5) * t.s[s][c];
+          if (inside) loc0.s[s][c] = loc0.s[s][c] - 0.5 * t.s[s][c];
+        }
+      store_spinor(out9 + (1 + 2 * mu + dir) * fs, g, b, l, o);
+    }
+  }
+  store_spinor(out9, g, b, l, loc0);
+}
+
+struct TauArr {
+  double t[QMG_MAXRHS];
+};
+
+template <typename S, typename C, int T>
+__global__ __launch_bounds__(64) void k_coarse_apply(Geom g, typename PT<C>::stor* out, const typename PT<S>::stor* DcT,
+                                                     const typename PT<C>::stor* in, int nc, int nrhs, TauArr tau) {
+  using R = typename PT<C>::real;
+  __shared__ cpx<R> xin[9][T][64];
+  const int b = blockIdx.x, k0 = blockIdx.y * T, tid = threadIdx.x;
+  for (int idx = tid; idx < 9 * T * nc; idx += blockDim.x) {
+    const int d = idx / (T * nc), t = (idx / nc) % T, j = idx % nc;
+    const int nbk = d == 0 ? b : g.nbr[b * 8 + d - 1];
+    const int k = k0 + t;
+    xin[d][t][j] = k < nrhs ? ldcv<R>(in, ((int64_t)k * g.nb + nbk) * nc + j) : czero<R>();
+  }
+  __syncthreads();
+  const int i = tid;
+  if (i >= nc) return;
+  cpx<R> acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = czero<R>();
+  const auto* Db = DcT + (int64_t)b * 9 * nc * nc;
+  for (int d = 0; d < 9; ++d)
+    for (int j = 0; j < nc; ++j) {
+      cpx<R> a = ldcv<R>(Db, ((int64_t)d * nc + j) * nc + i);
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[t] = acc[t] + a * xin[d][t][j];
+    }
+  const R g5 = i < nc / 2 ? R(1) : R(-1);
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int k = k0 + t;
+    if (k < nrhs) stcv(out, ((int64_t)k * g.nb + b) * nc + i, acc[t] - (R(tau.t[k]) * g5) * xin[0][t][i]);
+  }
+}
+
+template <typename S, int T>
+void capply_t(const qmg_ctx* c, int p, void* out, const void* in, const double* htau, int nrhs, hipStream_t s) {
+  using P = typename PT<S>::stor;
+  TauArr dtau;
+  for (int i = 0; i < QMG_MAXRHS; ++i) dtau.t[i] = i < nrhs ? htau[i] : 0.0;
+  const int nc = 2 * c->ntv;
+  dim3 grid(c->g.nb, (nrhs + T - 1) / T);
+  if (p == QMG_F64)
+    hipLaunchKernelGGL((k_coarse_apply<S, double, T>), grid, dim3(64), 0, s, c->g, (double2*)out,
+                       (const P*)c->Dc[p], (const double2*)in, nc, nrhs, dtau);
+  else
+    hipLaunchKernelGGL((k_coarse_apply<S, float, T>), grid, dim3(64), 0, s, c->g, (float2*)out,
+                       (const P*)c->Dc[p], (const float2*)in, nc, nrhs, dtau);
+}
+
+template <typename S>
+void capply_s(const qmg_ctx* c, int p, void* out, const void* in, const double* dtau, int nrhs, hipStream_t s) {
+  if (nrhs >= 4) capply_t<S, 4>(c, p, out, in, dtau, nrhs, s);
+  else if (nrhs == 2) capply_t<S, 2>(c, p, out, in, dtau, nrhs, s);
+  else capply_t<S, 1>(c, p, out, in, dtau, nrhs, s);
+}
+
+}  // namespace
+
+hipError_t launch_split_stencil(const qmg_ctx* c, void* out9, const void* in, hipStream_t s) {
+  hipLaunchKernelGGL(k_split, dim3((unsigned)((c->g.V + 255) / 256)), dim3(256), 0, s, c->g, (double2*)out9,
+                     (const double2*)in, (const double2*)c->U[QMG_F64], (const double2*)c->Dg[QMG_F64],
+                     c->m0 + 4.0, c->clover ? 1 : 0);
+  return hipGetLastError();
+}
+
+// tau: host array of nrhs shifts
+hipError_t launch_coarse_apply(const qmg_ctx* c, int p, void* out, const void* in, const double* dtau, int nrhs,
+                               hipStream_t s) {
+  if (p == QMG_F64) capply_s<double>(c, p, out, in, dtau, nrhs, s);
+  else if (p == QMG_F32) capply_s<float>(c, p, out, in, dtau, nrhs, s);
+  else capply_s<bf16_t>(c, p, out, in, dtau, nrhs, s);
+  return hipGetLastError();
+}

@@ -1,0 +1,147 @@
+// Wilson(-clover) stencil, eq. (2.5):
+//   (D psi)(x) = [(m0+4) + C(x)] psi(x) - 1/2 sum_mu (I - g_mu) U_mu(x) psi(x+mu)
+//                                       - 1/2 sum_mu (I + g_mu) U_mu(x-mu)^H psi(x-mu)
+// with the shift folded in: mode 0 gives (D - tau Gamma5) psi (eq. (3.7)),
+// mode 1 gives (Gamma5 D - tau) psi = (Q - tau) psi (eq. (1.1)).
+//
+// One thread per site and right-hand side.  Work-groups are mapped to sites
+// so that each XCD walks a contiguous slab of the block-major lattice and the
+// right-hand sides of one site tile run back to back on the same XCD (their
+// shared links then come from that XCD's L2).
+#include "qmg_ctx.h"
+
+namespace {
+
+template <typename S>
+struct DsArgs {
+  typename PT<S>::stor* out;
+  const typename PT<S>::stor* in;
+  const typename PT<S>::stor* U;
+  const typename PT<S>::stor* diag;
+  double mass4;
+  int64_t fstride;  // complex elements per field
+  int nrhs;
+  int remap;
+  Geom g;
+  double tau[QMG_MAXRHS];
+};
+
+// acc += (I - g_mu) U_mu(x) psi(x+mu) + (I + g_mu) U_mu(x-mu)^H psi(x-mu)
+template <typename R, int MU, typename P>
+__device__ __forceinline__ void hop_pair(Spinor<R>& acc, const P* in, const P* U, const Geom& g, int b, int l) {
+  int bn, ln;
+  nb_fwd(g, b, l, MU, bn, ln);
+  {
+    Half<R> h = project(load_spinor<R>(in, g, bn, ln), MU, true);
+    accum_recon(acc, umul(load_link<R>(U, g, b, MU, l), h), MU, true);
+  }
+  nb_bwd(g, b, l, MU, bn, ln);
+  {
+    Half<R> h = project(load_spinor<R>(in, g, bn, ln), MU, false);
+    accum_recon(acc, udagmul(load_link<R>(U, g, bn, MU, ln), h), MU, false);
+  }
+}
+
+template <typename S, bool CLOVER, int MODE, bool UB>
+__global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a) {
+  using R = typename PT<S>::real;
+  const Geom& g = a.g;
+  const int w = blockIdx.x, nw = gridDim.x;
+  const int L = (a.remap && (nw & 7) == 0) ? (w & 7) * (nw >> 3) + (w >> 3) : w;
+  const int k = L % a.nrhs;
+  const int64_t site = (int64_t)(L / a.nrhs) * blockDim.x + threadIdx.x;
+  if (site >= g.V) return;
+  int b = (int)(site >> g.bs_log);
+  if (UB) b = __builtin_amdgcn_readfirstlane(b);
+  const int l = (int)(site & ((1 << g.bs_log) - 1));
+  const auto* in = a.in + k * a.fstride;
+  auto* out = a.out + k * a.fstride;
+
+  Spinor<R> acc;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc.s[s][c] = czero<R>();
+
+  // one direction at a time keeps a single neighbour in flight per thread
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    switch (mu) {
+      case 0: hop_pair<R, 0>(acc, in, a.U, g, b, l); break;
+      case 1: hop_pair<R, 1>(acc, in, a.U, g, b, l); break;
+      case 2: hop_pair<R, 2>(acc, in, a.U, g, b, l); break;
+      default: hop_pair<R, 3>(acc, in, a.U, g, b, l); break;
+    }
+  }
+  const Spinor<R> self = load_spinor<R>(in, g, b, l);
+  Spinor<R> o;
+  if (CLOVER) {
+    o = apply_diag<R>(a.diag, g, b, l, self);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o.s[s][c] = R(a.mass4) * self.s[s][c];
+  }
+  const R tau = R(a.tau[k]);
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      cpx<R> v = o.s[s][c] - R(0.5) * acc.s[s][c];
+      if (MODE == 0) {
+        // D - tau Gamma5
+        v = (s < 2) ? v - tau * self.s[s][c] : v + tau * self.s[s][c];
+      } else {
+        // Gamma5 D - tau
+        v = (s < 2) ? v - tau * self.s[s][c] : -v - tau * self.s[s][c];
+      }
+      o.s[s][c] = v;
+    }
+  store_spinor(out, g, b, l, o);
+}
+
+template <typename S, bool CLOVER, int MODE>
+void launch_t(const qmg_ctx* c, void* out, const void* in, const double* tau, int nrhs, hipStream_t s,
+              int p) {
+  using P = typename PT<S>::stor;
+  DsArgs<S> a;
+  a.out = (P*)out;
+  a.in = (const P*)in;
+  a.U = (const P*)c->U[p];
+  a.diag = (const P*)c->Dg[p];
+  a.mass4 = c->m0 + 4.0;
+  a.fstride = (int64_t)field_elems(c);
+  a.nrhs = nrhs;
+  a.remap = c->tune.dslash_xcd_remap;
+  a.g = c->g;
+  for (int i = 0; i < QMG_MAXRHS; ++i) a.tau[i] = i < nrhs ? tau[i] : 0.0;
+  const int wg = 256;
+  unsigned nwg = (unsigned)((c->g.V + wg - 1) / wg) * (unsigned)nrhs;
+  if ((1 << c->g.bs_log) >= wg)
+    hipLaunchKernelGGL((k_dslash<S, CLOVER, MODE, true>), dim3(nwg), dim3(wg), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_dslash<S, CLOVER, MODE, false>), dim3(nwg), dim3(wg), 0, s, a);
+}
+
+template <typename S>
+void launch_p(const qmg_ctx* c, void* out, const void* in, const double* tau, int nrhs, int mode,
+              hipStream_t s, int p) {
+  if (c->clover) {
+    if (mode == 0) launch_t<S, true, 0>(c, out, in, tau, nrhs, s, p);
+    else launch_t<S, true, 1>(c, out, in, tau, nrhs, s, p);
+  } else {
+    if (mode == 0) launch_t<S, false, 0>(c, out, in, tau, nrhs, s, p);
+    else launch_t<S, false, 1>(c, out, in, tau, nrhs, s, p);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_dslash(const qmg_ctx* c, int p, void* out, const void* in, const double* tau, int nrhs,
+                         int mode, hipStream_t s) {
+  if (p == QMG_F64) launch_p<double>(c, out, in, tau, nrhs, mode, s, p);
+  else if (p == QMG_F32) launch_p<float>(c, out, in, tau, nrhs, mode, s, p);
+  else launch_p<bf16_t>(c, out, in, tau, nrhs, mode, s, p);
+  return hipGetLastError();
+}

@@ -1,0 +1,118 @@
+// Host-side context and the launchers each kernel file provides.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/qmg.h"
+#include "qmg_device.h"
+
+#define QMG_MAXRHS 64
+
+// size in bytes of one complex number in storage precision p
+inline size_t cbytes(int p) { return p == QMG_F64 ? 16 : (p == QMG_F32 ? 8 : 4); }
+// coarse vectors are double for F64 and float otherwise
+inline int coarse_prec(int p) { return p == QMG_F64 ? QMG_F64 : QMG_F32; }
+
+struct Tune {
+  int dslash_wg = 256;       // work-group size of the stencil
+  int dslash_xcd_remap = 1;  // XCD-aware mapping of work-groups to blocks
+  int sap_variant = 0;
+  int coarse_rhs_tile = 4;   // right-hand sides per coarse-apply work-group
+};
+
+struct qmg_ctx {
+  int device = 0;
+  Geom g{};                    // device pointers for tables inside
+  int* d_nbr = nullptr;
+  int* d_bcoord = nullptr;
+  std::vector<int> h_nbr, h_bcoord;
+  std::vector<int64_t> lex_of_block;
+  bool sap_ok = false;
+  // gauge
+  bool have_gauge = false;
+  double m0 = 0, csw = 0;
+  bool clover = false;
+  void* U[3] = {nullptr, nullptr, nullptr};
+  void* Dg[3] = {nullptr, nullptr, nullptr};
+  // multigrid
+  bool have_mg = false;
+  int ntv = 0;
+  void* P[3] = {nullptr, nullptr, nullptr};
+  void* Dc[3] = {nullptr, nullptr, nullptr};
+  // workspace
+  std::map<std::string, std::pair<void*, size_t>> ws;
+  std::map<std::string, std::vector<double>> hbuf;  // host staging for small Krylov data
+  std::string err;
+  Tune tune;
+  hipGraphExec_t graph = nullptr;
+  std::string graph_key;
+};
+
+size_t field_elems(const qmg_ctx* c);   // complex elements in one fine field
+size_t coarse_elems(const qmg_ctx* c);  // complex elements in one coarse vector
+
+// named, lazily grown device workspace (never shrinks; freed by qmg_destroy)
+void* ws_get(qmg_ctx* c, const std::string& name, size_t bytes);
+void ws_release(qmg_ctx* c, const std::string& name);
+
+// ---- layout.hip
+hipError_t launch_pack(const Geom& g, void* out, int p, const double* canon, int nrhs, hipStream_t s);
+hipError_t launch_unpack(const Geom& g, double* canon, const void* in, int p, int nrhs, hipStream_t s);
+hipError_t launch_convert(void* dst, int pd, const void* src, int ps, int64_t n, hipStream_t s);
+// ---- gauge.hip
+hipError_t launch_pack_gauge(const Geom& g, void* U64, const double* canon, hipStream_t s);
+hipError_t launch_clover(const Geom& g, void* diag64, const void* U64, double m0, double csw,
+                         hipStream_t s);
+// ---- dslash.hip   mode 0: (D - tau Gamma5), mode 1: (Gamma5 D - tau)
+hipError_t launch_dslash(const qmg_ctx* c, int p, void* out, const void* in, const double* tau,
+                         int nrhs, int mode, hipStream_t s);
+// ---- sap.hip
+hipError_t launch_sap_colour(const qmg_ctx* c, int p, void* x, const void* f, const double* tau,
+                             int nrhs, int colour, int n_mr, hipStream_t s);
+// ---- transfer.hip
+hipError_t launch_build_P(const qmg_ctx* c, void* P64, const void* W, int ntv, int* d_fail,
+                          hipStream_t s);
+hipError_t launch_restrict(const qmg_ctx* c, int p, void* yc, const void* v, int nrhs, hipStream_t s);
+hipError_t launch_prolong(const qmg_ctx* c, int p, void* v, const void* yc, int nrhs, hipStream_t s);
+// ---- coarse.hip
+hipError_t launch_split_stencil(const qmg_ctx* c, void* out9, const void* in, hipStream_t s);
+hipError_t launch_restrict_into_dc(const qmg_ctx* c, void* Dc64, const void* in9, int col,
+                                   hipStream_t s);
+hipError_t launch_coarse_apply(const qmg_ctx* c, int p, void* out, const void* in, const double* tau,
+                               int nrhs, hipStream_t s);  // tau: host array
+// ---- blas.hip (vectors of n complex per right-hand side, k-th rhs at offset k*stride)
+// dots[k*J + j] = <V_j,k , w_k> for j < J (V_j at base + j*vstride), FP64 results on device
+hipError_t launch_multidot(int p, double* dots, const void* V, int64_t vstride, int J, const void* w,
+                           int64_t n, int64_t stride, int nrhs, double* partial, hipStream_t s);
+// w_k += sum_j coef[k*J + j] * V_j,k   (coef complex double on device)
+hipError_t launch_multiaxpy(int p, void* w, const void* V, int64_t vstride, int J, const double* coef,
+                            int64_t n, int64_t stride, int nrhs, hipStream_t s);
+// y_k = a_k * x_k (a complex double on device, may alias)
+hipError_t launch_scale(int p, void* y, const void* x, const double* a, int64_t n, int64_t stride,
+                        int nrhs, hipStream_t s);
+// y_k = x_k - y_k  (xmy) or y_k = y_k + x_k
+hipError_t launch_xmy(int p, void* y, const void* x, int64_t n, int64_t stride, int nrhs, hipStream_t s);
+hipError_t launch_gamma5_bs(int p, void* y, const void* x, int64_t n, int bs_log, hipStream_t s);
+size_t multidot_partial_doubles(int64_t n, int J, int nrhs);
+hipError_t launch_fill_zero(void* y, size_t bytes, hipStream_t s);
+// ---- force.hip
+hipError_t launch_unit_coarse(void* y, int nb, int nc, int col, hipStream_t s);
+hipError_t launch_force(const qmg_ctx* c, double* dU, double* dUb, const void* phi, const void* x,
+                        hipStream_t s);
+
+// ---- solver.hip
+qmg_status solver_coarse_gmres(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs,
+                               int iters, double tol, int* iters_done, hipStream_t s);
+qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs,
+                         const qmg_params* prm, int* coarse_iters, hipStream_t s);
+qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, int nrhs,
+                         const qmg_params* prm, qmg_stats* st, hipStream_t s);
+qmg_status build_mg(qmg_ctx* c, const void* W, int ntv, hipStream_t s);
+qmg_status solver_setup(qmg_ctx* c, void* W, int ntv, int iters, int smooth, int n_mr, int kc,
+                        double ctol, hipStream_t s);
+qmg_status tune_run(qmg_ctx* c, const char* path);
+
+qmg_status set_err(qmg_ctx* c, qmg_status st, const std::string& msg);
+qmg_status hip_err(qmg_ctx* c, hipError_t e, const char* where);

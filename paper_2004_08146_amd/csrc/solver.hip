@@ -1,0 +1,491 @@
+// Krylov drivers: FGMRES (outer, FP64) preconditioned by the two-level
+// V-cycle (SAP smoother, aggregation coarse grid solved by GMRES), the
+// multigrid setup, and the assembly of P and D_c.
+//
+// Outer method: right-preconditioned flexible GMRES (Sec. 2 names FGMRES with
+// a multigrid preconditioner) on the Gamma5-preconditioned system
+// (D - tau Gamma5) x = Gamma5 b (eq. (3.6) <=> eq. (3.7)).  Arnoldi uses
+// classical Gram-Schmidt applied twice (CGS2) with batched dot products; the
+// small least-squares problems are solved on the host with complex Givens
+// rotations.  Each right-hand side runs its own Krylov space; the batch
+// advances in lock step and finished columns are frozen (their basis vectors
+// are zero, so every kernel still sees a fixed batch shape).
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "qmg_ctx.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+struct Lsq {
+  int m = 0;
+  std::vector<cd> H, g, sn;
+  std::vector<double> cs;
+  void init(int m_, double beta) {
+    m = m_;
+    H.assign((size_t)(m + 1) * m, cd(0));
+    g.assign(m + 1, cd(0));
+    g[0] = beta;
+    cs.assign(m, 0.0);
+    sn.assign(m, cd(0));
+  }
+  // add Hessenberg column j (h has j+2 entries); returns |g[j+1]|
+  double update(int j, std::vector<cd> h) {
+    for (int i = 0; i < j; ++i) {
+      cd t = cs[i] * h[i] + sn[i] * h[i + 1];
+      h[i + 1] = -std::conj(sn[i]) * h[i] + cs[i] * h[i + 1];
+      h[i] = t;
+    }
+    double c;
+    cd s;
+    const cd a = h[j], b = h[j + 1];
+    if (b == cd(0)) { c = 1.0; s = 0.0; }
+    else if (a == cd(0)) { c = 0.0; s = 1.0; }
+    else {
+      const double rho = std::sqrt(std::norm(a) + std::norm(b));
+      c = std::abs(a) / rho;
+      s = (a / std::abs(a)) * std::conj(b) / rho;
+    }
+    cs[j] = c;
+    sn[j] = s;
+    h[j] = c * h[j] + s * h[j + 1];
+    h[j + 1] = 0.0;
+    g[j + 1] = -std::conj(s) * g[j];
+    g[j] = c * g[j];
+    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
+    return std::abs(g[j + 1]);
+  }
+  std::vector<cd> solve(int k) const {
+    std::vector<cd> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+      cd t = g[i];
+      for (int l = i + 1; l < k; ++l) t -= H[(size_t)i * m + l] * y[l];
+      y[i] = t / H[(size_t)i * m + i];
+    }
+    return y;
+  }
+};
+
+double* host_buf(qmg_ctx* c, const std::string& name, size_t ndouble) {
+  auto& v = c->hbuf[name];
+  if (v.size() < ndouble) v.resize(ndouble);
+  return v.data();
+}
+
+// batched vector space helper (n complex per vector, nrhs vectors per batch)
+struct Space {
+  qmg_ctx* c;
+  int p;
+  int64_t n;
+  int nrhs;
+  hipStream_t s;
+  size_t vbytes() const { return (size_t)n * cbytes(p); }
+  size_t bbytes() const { return vbytes() * nrhs; }
+  char* at(void* base, int j) const { return (char*)base + (size_t)j * bbytes(); }
+  int64_t vstride() const { return n * nrhs; }
+
+  // out[k*J + j] = <V_j,k, w_k>
+  qmg_status dots(std::vector<cd>& out, const void* V, int J, int64_t vstr, const void* w) {
+    double* d = (double*)ws_get(c, "sp_dots", sizeof(double) * 2 * J * nrhs);
+    double* part = (double*)ws_get(c, "sp_part", sizeof(double) * multidot_partial_doubles(n, J, nrhs));
+    if (!d || !part) return set_err(c, QMG_E_NOMEM, "out of device memory (dots)");
+    hipError_t e = launch_multidot(p, d, V, vstr, J, w, n, n, nrhs, part, s);
+    if (e != hipSuccess) return hip_err(c, e, "multidot");
+    double* h = host_buf(c, "dots", 2 * J * nrhs);
+    e = hipMemcpyAsync(h, d, sizeof(double) * 2 * J * nrhs, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(c, e, "dots D2H");
+    out.resize((size_t)J * nrhs);
+    for (int i = 0; i < J * nrhs; ++i) out[i] = cd(h[2 * i], h[2 * i + 1]);
+    return QMG_OK;
+  }
+  qmg_status norms(std::vector<double>& out, const void* w) {
+    std::vector<cd> d;
+    qmg_status st = dots(d, w, 1, 0, w);
+    if (st != QMG_OK) return st;
+    out.resize(nrhs);
+    for (int k = 0; k < nrhs; ++k) out[k] = std::sqrt(std::max(0.0, d[k].real()));
+    return QMG_OK;
+  }
+  // w_k += sum_j coef[k*J + j] V_j,k
+  qmg_status axpy(void* w, const void* V, int J, int64_t vstr, const std::vector<cd>& coef) {
+    double* d = (double*)ws_get(c, "sp_coef", sizeof(double) * 2 * J * nrhs);
+    if (!d) return set_err(c, QMG_E_NOMEM, "out of device memory (coef)");
+    double* h = host_buf(c, "coef", 2 * J * nrhs);
+    for (int i = 0; i < J * nrhs; ++i) { h[2 * i] = coef[i].real(); h[2 * i + 1] = coef[i].imag(); }
+    hipError_t e = hipMemcpyAsync(d, h, sizeof(double) * 2 * J * nrhs, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_multiaxpy(p, w, V, vstr, J, d, n, n, nrhs, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host coef buffer is reused next call
+    if (e != hipSuccess) return hip_err(c, e, "axpy");
+    return QMG_OK;
+  }
+  qmg_status scale(void* y, const void* x, const std::vector<cd>& a) {
+    double* d = (double*)ws_get(c, "sp_scale", sizeof(double) * 2 * nrhs);
+    if (!d) return set_err(c, QMG_E_NOMEM, "out of device memory (scale)");
+    double* h = host_buf(c, "scale", 2 * nrhs);
+    for (int k = 0; k < nrhs; ++k) { h[2 * k] = a[k].real(); h[2 * k + 1] = a[k].imag(); }
+    hipError_t e = hipMemcpyAsync(d, h, sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_scale(p, y, x, d, n, n, nrhs, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(c, e, "scale");
+    return QMG_OK;
+  }
+  // one CGS2 Arnoldi step on basis V_0..V_j with new vector w; h[k] gets j+2 entries
+  qmg_status arnoldi(std::vector<std::vector<cd>>& h, void* V, int j, void* w) {
+    const int J = j + 1;
+    h.assign(nrhs, std::vector<cd>(j + 2, cd(0)));
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<cd> d;
+      qmg_status st = dots(d, V, J, vstride(), w);
+      if (st != QMG_OK) return st;
+      std::vector<cd> coef(d.size());
+      for (int k = 0; k < nrhs; ++k)
+        for (int i = 0; i < J; ++i) {
+          h[k][i] += d[(size_t)k * J + i];
+          coef[(size_t)k * J + i] = -d[(size_t)k * J + i];
+        }
+      st = axpy(w, V, J, vstride(), coef);
+      if (st != QMG_OK) return st;
+    }
+    std::vector<double> nn;
+    qmg_status st = norms(nn, w);
+    if (st != QMG_OK) return st;
+    for (int k = 0; k < nrhs; ++k) {
+      if (!std::isfinite(nn[k])) return set_err(c, QMG_E_NUMERIC, "non-finite norm in Arnoldi step");
+      h[k][j + 1] = nn[k];
+    }
+    return QMG_OK;
+  }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------ coarse GMRES --
+qmg_status solver_coarse_gmres(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
+                               double tol, int* iters_done, hipStream_t s) {
+  const int cp = coarse_prec(p);
+  Space sp{c, cp, (int64_t)coarse_elems(c), nrhs, s};
+  if (iters < 1) iters = 1;
+  void* V = ws_get(c, "cg_V", sp.bbytes() * (iters + 1));
+  void* w = ws_get(c, "cg_w", sp.bbytes());
+  if (!V || !w) return set_err(c, QMG_E_NOMEM, "out of device memory (coarse GMRES)");
+  std::vector<double> beta;
+  qmg_status st = sp.norms(beta, r);
+  if (st != QMG_OK) return st;
+  std::vector<cd> a(nrhs);
+  std::vector<Lsq> lsq(nrhs);
+  std::vector<char> act(nrhs);
+  for (int k = 0; k < nrhs; ++k) {
+    if (!std::isfinite(beta[k])) return set_err(c, QMG_E_NUMERIC, "non-finite coarse right-hand side");
+    act[k] = beta[k] > 0;
+    a[k] = act[k] ? 1.0 / beta[k] : 0.0;
+    lsq[k].init(iters, beta[k]);
+  }
+  st = sp.scale(sp.at(V, 0), r, a);
+  if (st != QMG_OK) return st;
+  std::vector<int> kk(nrhs, 0);
+  int done_it = 0;
+  for (int j = 0; j < iters; ++j) {
+    hipError_t e = launch_coarse_apply(c, p, w, sp.at(V, j), tau, nrhs, s);
+    if (e != hipSuccess) return hip_err(c, e, "coarse apply");
+    std::vector<std::vector<cd>> h;
+    st = sp.arnoldi(h, V, j, w);
+    if (st != QMG_OK) return st;
+    bool all = true;
+    for (int k = 0; k < nrhs; ++k) {
+      if (!act[k]) { a[k] = 0.0; continue; }
+      double est = lsq[k].update(j, h[k]);
+      kk[k] = j + 1;
+      const double hn = h[k][j + 1].real();
+      if (hn == 0.0 || (tol > 0 && est <= tol * beta[k])) act[k] = 0;
+      a[k] = act[k] ? 1.0 / hn : 0.0;
+      all = all && !act[k];
+    }
+    done_it = j + 1;
+    if (all || j + 1 == iters) break;
+    st = sp.scale(sp.at(V, j + 1), w, a);
+    if (st != QMG_OK) return st;
+  }
+  int J = 0;
+  for (int k = 0; k < nrhs; ++k) J = std::max(J, kk[k]);
+  hipError_t e = launch_fill_zero(y, sp.bbytes(), s);
+  if (e != hipSuccess) return hip_err(c, e, "zero");
+  if (J > 0) {
+    std::vector<cd> coef((size_t)J * nrhs, cd(0));
+    for (int k = 0; k < nrhs; ++k) {
+      if (kk[k] == 0) continue;
+      std::vector<cd> yk = lsq[k].solve(kk[k]);
+      for (int i = 0; i < kk[k]; ++i) coef[(size_t)k * J + i] = yk[i];
+    }
+    st = sp.axpy(y, V, J, sp.vstride(), coef);
+    if (st != QMG_OK) return st;
+  }
+  if (iters_done) *iters_done = done_it;
+  return QMG_OK;
+}
+
+// ----------------------------------------------------------------- V-cycle --
+qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
+                         int* coarse_iters, hipStream_t s) {
+  const int p = prm->mg_prec;
+  const int64_t n = (int64_t)field_elems(c);
+  void* rp = (void*)r;
+  void* zp = z;
+  hipError_t e;
+  if (p != QMG_F64) {
+    rp = ws_get(c, "vc_r", (size_t)n * nrhs * cbytes(p));
+    zp = ws_get(c, "vc_z", (size_t)n * nrhs * cbytes(p));
+    if (!rp || !zp) return set_err(c, QMG_E_NOMEM, "out of device memory (V-cycle)");
+    e = launch_convert(rp, p, r, QMG_F64, n * nrhs, s);
+    if (e != hipSuccess) return hip_err(c, e, "convert");
+  }
+  if (prm->use_coarse && c->have_mg) {
+    const int cp = coarse_prec(p);
+    const size_t cb = coarse_elems(c) * cbytes(cp) * nrhs;
+    void* rc = ws_get(c, "vc_rc", cb);
+    void* yc = ws_get(c, "vc_yc", cb);
+    if (!rc || !yc) return set_err(c, QMG_E_NOMEM, "out of device memory (V-cycle)");
+    e = launch_restrict(c, p, rc, rp, nrhs, s);
+    if (e != hipSuccess) return hip_err(c, e, "restrict");
+    int it = 0;
+    qmg_status st = solver_coarse_gmres(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, prm->coarse_tol, &it, s);
+    if (st != QMG_OK) return st;
+    if (coarse_iters) *coarse_iters += it;
+    e = launch_prolong(c, p, zp, yc, nrhs, s);
+    if (e != hipSuccess) return hip_err(c, e, "prolong");
+  } else {
+    e = launch_fill_zero(zp, (size_t)n * nrhs * cbytes(p), s);
+    if (e != hipSuccess) return hip_err(c, e, "zero");
+  }
+  for (int sw = 0; sw < prm->nu_post; ++sw)
+    for (int col = 0; col < 2; ++col) {
+      e = launch_sap_colour(c, p, zp, rp, tau, nrhs, col, prm->n_mr, s);
+      if (e != hipSuccess) return hip_err(c, e, "sap");
+    }
+  if (p != QMG_F64) {
+    e = launch_convert(z, QMG_F64, zp, p, n * nrhs, s);
+    if (e != hipSuccess) return hip_err(c, e, "convert");
+  }
+  return QMG_OK;
+}
+
+// ------------------------------------------------------------------ FGMRES --
+qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, int nrhs, const qmg_params* prm,
+                         qmg_stats* stats, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int m = std::max(1, prm->restart);
+  Space sp{c, QMG_F64, (int64_t)field_elems(c), nrhs, s};
+  const size_t bb = sp.bbytes();
+  void* V = ws_get(c, "fg_V", bb * (m + 1));
+  void* Z = ws_get(c, "fg_Z", bb * m);
+  void* f = ws_get(c, "fg_f", bb);
+  void* r = ws_get(c, "fg_r", bb);
+  void* w = ws_get(c, "fg_w", bb);
+  if (!V || !Z || !f || !r || !w) return set_err(c, QMG_E_NOMEM, "out of device memory (FGMRES)");
+  hipError_t e = launch_gamma5_bs(QMG_F64, f, b, sp.n * nrhs, c->g.bs_log, s);
+  if (e == hipSuccess) e = launch_fill_zero(x, bb, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(r, f, bb, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_err(c, e, "fgmres init");
+  std::vector<double> bnorm, beta;
+  qmg_status st = sp.norms(bnorm, b);
+  if (st != QMG_OK) return st;
+  for (int k = 0; k < nrhs; ++k)
+    if (!std::isfinite(bnorm[k])) return set_err(c, QMG_E_NUMERIC, "non-finite right-hand side");
+  std::vector<int> iters(nrhs, 0), restarts(nrhs, 0), cits(nrhs, 0);
+  std::vector<double> relres(nrhs, 0.0);
+  int total = 0;
+  while (true) {
+    st = sp.norms(beta, r);
+    if (st != QMG_OK) return st;
+    std::vector<char> act(nrhs);
+    bool any = false;
+    for (int k = 0; k < nrhs; ++k) {
+      if (!std::isfinite(beta[k])) return set_err(c, QMG_E_NUMERIC, "non-finite residual");
+      relres[k] = bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0;
+      act[k] = relres[k] > prm->tol;
+      any = any || act[k];
+    }
+    if (!any || total >= prm->maxiter) break;
+    std::vector<cd> a(nrhs);
+    std::vector<Lsq> lsq(nrhs);
+    for (int k = 0; k < nrhs; ++k) {
+      a[k] = act[k] ? 1.0 / beta[k] : 0.0;
+      lsq[k].init(m, beta[k]);
+      if (act[k]) restarts[k] += 1;
+    }
+    st = sp.scale(sp.at(V, 0), r, a);
+    if (st != QMG_OK) return st;
+    std::vector<int> kk(nrhs, 0);
+    for (int j = 0; j < m; ++j) {
+      int ci = 0;
+      st = solver_vcycle(c, sp.at(Z, j), sp.at(V, j), tau, nrhs, prm, &ci, s);
+      if (st != QMG_OK) return st;
+      e = launch_dslash(c, QMG_F64, w, sp.at(Z, j), tau, nrhs, 0, s);
+      if (e != hipSuccess) return hip_err(c, e, "apply");
+      std::vector<std::vector<cd>> h;
+      st = sp.arnoldi(h, V, j, w);
+      if (st != QMG_OK) return st;
+      bool all = true;
+      for (int k = 0; k < nrhs; ++k) {
+        if (!act[k]) { a[k] = 0.0; continue; }
+        double est = lsq[k].update(j, h[k]);
+        kk[k] = j + 1;
+        iters[k] += 1;
+        cits[k] += ci;
+        const double hn = h[k][j + 1].real();
+        if (hn == 0.0 || est <= prm->tol * bnorm[k]) act[k] = 0;
+        a[k] = act[k] ? 1.0 / hn : 0.0;
+        all = all && !act[k];
+      }
+      ++total;
+      if (all || j + 1 == m || total >= prm->maxiter) break;
+      st = sp.scale(sp.at(V, j + 1), w, a);
+      if (st != QMG_OK) return st;
+    }
+    int J = 0;
+    for (int k = 0; k < nrhs; ++k) J = std::max(J, kk[k]);
+    if (J > 0) {
+      std::vector<cd> coef((size_t)J * nrhs, cd(0));
+      for (int k = 0; k < nrhs; ++k) {
+        if (kk[k] == 0) continue;
+        std::vector<cd> yk = lsq[k].solve(kk[k]);
+        for (int i = 0; i < kk[k]; ++i) {
+          if (!std::isfinite(yk[i].real()) || !std::isfinite(yk[i].imag()))
+            return set_err(c, QMG_E_NUMERIC, "non-finite least-squares solution");
+          coef[(size_t)k * J + i] = yk[i];
+        }
+      }
+      st = sp.axpy(x, Z, J, sp.vstride(), coef);
+      if (st != QMG_OK) return st;
+    }
+    // true residual r = Gamma5 b - A_tau x
+    e = launch_dslash(c, QMG_F64, r, x, tau, nrhs, 0, s);
+    if (e == hipSuccess) e = launch_xmy(QMG_F64, r, f, sp.n, sp.n, nrhs, s);
+    if (e != hipSuccess) return hip_err(c, e, "residual");
+  }
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c, e, "sync");
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  bool conv = true;
+  for (int k = 0; k < nrhs; ++k) {
+    conv = conv && relres[k] <= prm->tol;
+    if (stats) {
+      stats[k].iters = iters[k];
+      stats[k].restarts = restarts[k];
+      stats[k].coarse_iters = cits[k];
+      stats[k].true_relres = relres[k];
+      stats[k].seconds = secs;
+    }
+  }
+  return conv ? QMG_OK : QMG_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------- P and D_c assembly --
+qmg_status build_mg(qmg_ctx* c, const void* W, int ntv, hipStream_t s) {
+  const Geom& g = c->g;
+  const int nc = 2 * ntv;
+  const size_t pel = (size_t)g.nb * 2 * ntv * 6 * ((size_t)1 << g.bs_log);
+  const size_t del = (size_t)g.nb * 9 * nc * nc;
+  c->have_mg = false;
+  c->ntv = ntv;
+  for (int p = 0; p < 3; ++p) {
+    const std::string ps = std::to_string(p);
+    c->P[p] = ws_get(c, "mg_P" + ps, pel * cbytes(p));
+    c->Dc[p] = ws_get(c, "mg_Dc" + ps, del * cbytes(p));
+    if (!c->P[p] || !c->Dc[p]) return set_err(c, QMG_E_NOMEM, "out of device memory (P, D_c)");
+  }
+  int* fail = (int*)ws_get(c, "mg_fail", sizeof(int));
+  if (!fail) return set_err(c, QMG_E_NOMEM, "out of device memory");
+  hipError_t e = hipMemsetAsync(fail, 0, sizeof(int), s);
+  if (e == hipSuccess) e = launch_build_P(c, c->P[QMG_F64], W, ntv, fail, s);
+  int hfail = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hfail, fail, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c, e, "build P");
+  if (hfail) return set_err(c, QMG_E_NUMERIC, "test vectors are locally rank deficient");
+  // D_c column by column
+  void* ycol = ws_get(c, "mg_ycol", coarse_elems(c) * 16);
+  void* pcol = ws_get(c, "mg_pcol", field_elems(c) * 16);
+  void* nine = ws_get(c, "mg_nine", field_elems(c) * 16 * 9);
+  if (!ycol || !pcol || !nine) return set_err(c, QMG_E_NOMEM, "out of device memory (D_c assembly)");
+  for (int col = 0; col < nc; ++col) {
+    e = launch_unit_coarse(ycol, g.nb, nc, col, s);
+    if (e == hipSuccess) e = launch_prolong(c, QMG_F64, pcol, ycol, 1, s);
+    if (e == hipSuccess) e = launch_split_stencil(c, nine, pcol, s);
+    if (e == hipSuccess) e = launch_restrict_into_dc(c, c->Dc[QMG_F64], nine, col, s);
+    if (e != hipSuccess) return hip_err(c, e, "assemble D_c");
+  }
+  for (int p = 1; p < 3; ++p) {
+    e = launch_convert(c->P[p], p, c->P[QMG_F64], QMG_F64, (int64_t)pel, s);
+    if (e == hipSuccess) e = launch_convert(c->Dc[p], p, c->Dc[QMG_F64], QMG_F64, (int64_t)del, s);
+    if (e != hipSuccess) return hip_err(c, e, "convert P/D_c");
+  }
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c, e, "sync");
+  c->have_mg = true;
+  return QMG_OK;
+}
+
+// ------------------------------------------------------------------- setup --
+// Reading of the paper's setup parameters (test vectors, setup iterations,
+// smoothing steps): smooth random W on D w = 0 with SAP, then repeat
+// V-cycle inverse iteration (tau = 0), rebuilding P and D_c after each round.
+qmg_status solver_setup(qmg_ctx* c, void* W, int ntv, int iters, int smooth, int n_mr, int kc, double ctol,
+                        hipStream_t s) {
+  const int64_t n = (int64_t)field_elems(c);
+  const size_t fb = (size_t)n * 16;
+  Space sp{c, QMG_F64, n, ntv, s};
+  std::vector<double> tau0(ntv, 0.0);
+  void* zero = ws_get(c, "su_zero", fb * ntv);
+  if (!zero) return set_err(c, QMG_E_NOMEM, "out of device memory (setup)");
+  hipError_t e = launch_fill_zero(zero, fb * ntv, s);
+  if (e != hipSuccess) return hip_err(c, e, "zero");
+  for (int sw = 0; sw < smooth; ++sw)
+    for (int col = 0; col < 2; ++col) {
+      e = launch_sap_colour(c, QMG_F64, W, zero, tau0.data(), ntv, col, n_mr, s);
+      if (e != hipSuccess) return hip_err(c, e, "setup sap");
+    }
+  auto normalise = [&](void* X) -> qmg_status {
+    std::vector<double> nn;
+    qmg_status st = sp.norms(nn, X);
+    if (st != QMG_OK) return st;
+    std::vector<cd> a(ntv);
+    for (int k = 0; k < ntv; ++k) {
+      if (!(nn[k] > 0) || !std::isfinite(nn[k])) return set_err(c, QMG_E_NUMERIC, "setup vector vanished");
+      a[k] = 1.0 / nn[k];
+    }
+    return sp.scale(X, X, a);
+  };
+  qmg_status st = normalise(W);
+  if (st != QMG_OK) return st;
+  st = build_mg(c, W, ntv, s);
+  if (st != QMG_OK) return st;
+  qmg_params prm = qmg_default_params();
+  prm.nu_post = smooth;
+  prm.n_mr = n_mr;
+  prm.coarse_maxiter = kc;
+  prm.coarse_tol = ctol;
+  prm.mg_prec = QMG_F32;
+  prm.use_coarse = 1;
+  void* Wn = ws_get(c, "su_new", fb * ntv);
+  if (!Wn) return set_err(c, QMG_E_NOMEM, "out of device memory (setup)");
+  for (int it = 1; it < iters; ++it) {
+    st = solver_vcycle(c, Wn, W, tau0.data(), ntv, &prm, nullptr, s);
+    if (st != QMG_OK) return st;
+    st = normalise(Wn);
+    if (st != QMG_OK) return st;
+    e = hipMemcpyAsync(W, Wn, fb * ntv, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_err(c, e, "copy");
+    st = build_mg(c, W, ntv, s);
+    if (st != QMG_OK) return st;
+  }
+  ws_release(c, "su_zero");
+  ws_release(c, "su_new");
+  ws_release(c, "mg_nine");
+  return QMG_OK;
+}

@@ -1,0 +1,183 @@
+// Interpolation P from test vectors, restriction y = P^H v and prolongation
+// v = P y (Sec. 2: aggregation-based P, R = P^H; Sec. 3.1 on building P).
+//
+// Aggregates are (lattice block) x (chirality half): spins {0,1} and {2,3},
+// so Gamma5 P = P Gamma5^c (text before eq. (2.9)).  P is stored complex
+// [nb][2][ntv][6][bs]: column j of aggregate (b, h), entry (spin-in-half,
+// colour) d at site l.  Coarse vectors are [nrhs][nb][2*ntv], index h*ntv + j.
+// Columns of each aggregate are orthonormalised with modified Gram-Schmidt,
+// applied twice per column, in column order.
+#include "qmg_ctx.h"
+#include "reduce.h"
+
+namespace {
+
+QMG_HD int64_t pidx(const Geom& g, int ntv, int b, int h, int j, int d, int l) {
+  return ((((int64_t)b * 2 + h) * ntv + j) * 6 + d) * ((int64_t)1 << g.bs_log) + l;
+}
+
+__global__ __launch_bounds__(256) void k_build_P(Geom g, double2* P, const double2* W, int ntv, int* fail) {
+  extern __shared__ double red[];
+  const int b = blockIdx.x, l = threadIdx.x;
+  const int64_t fs = g.V * 12;
+  for (int j = 0; j < ntv; ++j) {
+    cpx<double> v[2][6];
+    for (int h = 0; h < 2; ++h)
+      for (int d = 0; d < 6; ++d) v[h][d] = ldc(W + j * fs, sidx(g, b, 6 * h + d, l));
+    double n0[2] = {0, 0};
+    for (int h = 0; h < 2; ++h)
+      for (int d = 0; d < 6; ++d) n0[h] += norm2(v[h][d]);
+    wg_sum<double, 2>(n0, red);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < j; ++i) {
+        double cf[4] = {0, 0, 0, 0};
+        for (int h = 0; h < 2; ++h)
+          for (int d = 0; d < 6; ++d) {
+            cpx<double> t = cmul_conj(ldc(P, pidx(g, ntv, b, h, i, d, l)), v[h][d]);
+            cf[2 * h] += t.re;
+            cf[2 * h + 1] += t.im;
+          }
+        wg_sum<double, 4>(cf, red);
+        for (int h = 0; h < 2; ++h) {
+          cpx<double> c = {cf[2 * h], cf[2 * h + 1]};
+          for (int d = 0; d < 6; ++d) v[h][d] = v[h][d] - c * ldc(P, pidx(g, ntv, b, h, i, d, l));
+        }
+      }
+    double n1[2] = {0, 0};
+    for (int h = 0; h < 2; ++h)
+      for (int d = 0; d < 6; ++d) n1[h] += norm2(v[h][d]);
+    wg_sum<double, 2>(n1, red);
+    for (int h = 0; h < 2; ++h) {
+      double nn = sqrt(n1[h]);
+      if (!(nn >= 1e-12 * sqrt(n0[h]))) {
+        if (l == 0) fail[0] = 1;
+        nn = 1.0;
+      }
+      double inv = 1.0 / nn;
+      for (int d = 0; d < 6; ++d) stc(P, pidx(g, ntv, b, h, j, d, l), inv * v[h][d]);
+    }
+  }
+}
+
+// y[k][b][o] = sum_{l,d} conj(P[b][h][j][d][l]) v[k][b][6h+d][l], o = h*ntv + j
+template <typename S, typename C>
+__global__ __launch_bounds__(256) void k_restrict(Geom g, typename PT<C>::stor* y, const typename PT<S>::stor* P,
+                                                  const typename PT<S>::stor* v, int ntv, int nrhs,
+                                                  int64_t fstride, int64_t ysk, int64_t ysb) {
+  using R = typename PT<S>::real;
+  extern __shared__ unsigned char smem_r[];
+  R* red = reinterpret_cast<R*>(smem_r);
+  const int b = blockIdx.x / nrhs, k = blockIdx.x % nrhs, l = threadIdx.x;
+  const int nc = 2 * ntv;
+  cpx<R> vv[12];
+  for (int c = 0; c < 12; ++c) vv[c] = ldcv<R>(v + k * fstride, sidx(g, b, c, l));
+  auto* yo = y + k * ysk + b * ysb;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    for (int j0 = 0; j0 < ntv; j0 += 8) {
+      R acc[16];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int j = j0 + t;
+        cpx<R> s = czero<R>();
+        if (j < ntv)
+#pragma unroll
+          for (int d = 0; d < 6; ++d) s = s + cmul_conj(ldcv<R>(P, pidx(g, ntv, b, h, j, d, l)), vv[6 * h + d]);
+        acc[2 * t] = s.re;
+        acc[2 * t + 1] = s.im;
+      }
+      wg_sum<R, 16>(acc, red);
+      if (l < 8 && j0 + l < ntv) {
+        R re = acc[0], im = acc[1];
+#pragma unroll
+        for (int t = 1; t < 8; ++t)
+          if (t == l) { re = acc[2 * t]; im = acc[2 * t + 1]; }
+        stcv(yo, h * ntv + j0 + l, cpx<R>{re, im});
+      }
+    }
+}
+
+// v[k][b][6h+d][l] = sum_j P[b][h][j][d][l] y[k][b][h*ntv+j]
+template <typename S, typename C>
+__global__ __launch_bounds__(256) void k_prolong(Geom g, typename PT<S>::stor* v, const typename PT<S>::stor* P,
+                                                 const typename PT<C>::stor* y, int ntv, int nrhs,
+                                                 int64_t fstride) {
+  using R = typename PT<S>::real;
+  __shared__ cpx<R> ys[64];
+  const int b = blockIdx.x / nrhs, k = blockIdx.x % nrhs, l = threadIdx.x;
+  const int nc = 2 * ntv;
+  const auto* yi = y + ((int64_t)k * g.nb + b) * nc;
+  for (int o = l; o < nc; o += blockDim.x) ys[o] = ldcv<R>(yi, o);
+  __syncthreads();
+  for (int h = 0; h < 2; ++h)
+    for (int d = 0; d < 6; ++d) {
+      cpx<R> s = czero<R>();
+      for (int j = 0; j < ntv; ++j) s = s + ldcv<R>(P, pidx(g, ntv, b, h, j, d, l)) * ys[h * ntv + j];
+      stcv(v + k * fstride, sidx(g, b, 6 * h + d, l), s);
+    }
+}
+
+template <typename S>
+void restrict_t(const qmg_ctx* c, void* yc, const void* v, int nrhs, hipStream_t s, int p) {
+  using P = typename PT<S>::stor;
+  using R = typename PT<S>::real;
+  const int bs = 1 << c->g.bs_log;
+  size_t lds = sizeof(R) * 16 * std::max(bs, 4);
+  if (p == QMG_F64)
+    hipLaunchKernelGGL((k_restrict<S, double>), dim3(c->g.nb * nrhs), dim3(bs), lds, s, c->g, (double2*)yc,
+                       (const P*)c->P[p], (const P*)v, c->ntv, nrhs, (int64_t)field_elems(c),
+                       (int64_t)c->g.nb * 2 * c->ntv, (int64_t)2 * c->ntv);
+  else
+    hipLaunchKernelGGL((k_restrict<S, float>), dim3(c->g.nb * nrhs), dim3(bs), lds, s, c->g, (float2*)yc,
+                       (const P*)c->P[p], (const P*)v, c->ntv, nrhs, (int64_t)field_elems(c),
+                       (int64_t)c->g.nb * 2 * c->ntv, (int64_t)2 * c->ntv);
+}
+
+template <typename S>
+void prolong_t(const qmg_ctx* c, void* v, const void* yc, int nrhs, hipStream_t s, int p) {
+  using P = typename PT<S>::stor;
+  const int bs = 1 << c->g.bs_log;
+  if (p == QMG_F64)
+    hipLaunchKernelGGL((k_prolong<S, double>), dim3(c->g.nb * nrhs), dim3(bs), 0, s, c->g, (P*)v,
+                       (const P*)c->P[p], (const double2*)yc, c->ntv, nrhs, (int64_t)field_elems(c));
+  else
+    hipLaunchKernelGGL((k_prolong<S, float>), dim3(c->g.nb * nrhs), dim3(bs), 0, s, c->g, (P*)v,
+                       (const P*)c->P[p], (const float2*)yc, c->ntv, nrhs, (int64_t)field_elems(c));
+}
+
+}  // namespace
+
+hipError_t launch_build_P(const qmg_ctx* c, void* P64, const void* W, int ntv, int* d_fail, hipStream_t s) {
+  const int bs = 1 << c->g.bs_log;
+  size_t lds = sizeof(double) * 4 * std::max(bs, 4);
+  hipLaunchKernelGGL(k_build_P, dim3(c->g.nb), dim3(bs), lds, s, c->g, (double2*)P64, (const double2*)W, ntv,
+                     d_fail);
+  return hipGetLastError();
+}
+
+// Dc^T[b][d][col][:] = P_b^H in9[d]|_b for the 9 stencil parts d (column col of
+// every coarse block D_c[b][d], stored transposed)
+hipError_t launch_restrict_into_dc(const qmg_ctx* c, void* Dc64, const void* in9, int col, hipStream_t s) {
+  const int bs = 1 << c->g.bs_log;
+  const int nc = 2 * c->ntv;
+  size_t lds = sizeof(double) * 16 * std::max(bs, 4);
+  double2* base = (double2*)Dc64 + (int64_t)col * nc;
+  hipLaunchKernelGGL((k_restrict<double, double>), dim3(c->g.nb * 9), dim3(bs), lds, s, c->g, base,
+                     (const double2*)c->P[QMG_F64], (const double2*)in9, c->ntv, 9, (int64_t)field_elems(c),
+                     (int64_t)nc * nc, (int64_t)9 * nc * nc);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict(const qmg_ctx* c, int p, void* yc, const void* v, int nrhs, hipStream_t s) {
+  if (p == QMG_F64) restrict_t<double>(c, yc, v, nrhs, s, p);
+  else if (p == QMG_F32) restrict_t<float>(c, yc, v, nrhs, s, p);
+  else restrict_t<bf16_t>(c, yc, v, nrhs, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const qmg_ctx* c, int p, void* v, const void* yc, int nrhs, hipStream_t s) {
+  if (p == QMG_F64) prolong_t<double>(c, v, yc, nrhs, s, p);
+  else if (p == QMG_F32) prolong_t<float>(c, v, yc, nrhs, s, p);
+  else prolong_t<bf16_t>(c, v, yc, nrhs, s, p);
+  return hipGetLastError();
+}

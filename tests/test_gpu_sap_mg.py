@@ -1,0 +1,118 @@
+"""GPU parity of SAP, P, restriction/prolongation, D_c and the V-cycle."""
+import numpy as np
+import pytest
+
+from gpu_common import case, coarse_to_lex, dev, host, lex_to_coarse, need_gpu, torch
+from helpers import rel_err
+from oracle import clover as oclover
+from oracle import dirac, krylov, mg, sap
+from synth import random_links, random_spinors, random_test_vectors, seed_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _op(dims, block, csw=1.0, m0=-0.8, cfg=2):
+    qmg = need_gpu()
+    U = random_links(dims, 0.5, seed_for(cfg, "U"))
+    C = oclover.clover_term(U, csw) if csw else None
+    lat = qmg.Lattice(dims, block)
+    lat.set_gauge(dev(U), m0, csw)
+    return qmg, lat, dirac.Operator(U, m0, C)
+
+
+@pytest.mark.parametrize("dims,block", [((8, 8, 8, 8), (4, 4, 4, 4)), ((4, 4, 4, 4), (2, 2, 2, 2)),
+                                        ((8, 4, 4, 8), (4, 2, 2, 4))])
+def test_sap_parity(dims, block):
+    case("sap %s %s" % (dims, block))
+    qmg, lat, op = _op(dims, block)
+    nrhs = 2
+    f = random_spinors(dims, nrhs, seed_for(2, "b"))
+    x0 = random_spinors(dims, nrhs, seed_for(2, "x"))
+    taus = [0.01, 0.2]
+    xg = lat.pack(dev(x0))
+    lat.sap_smooth(xg, lat.pack(dev(f)), taus, nrhs, nsweep=2, n_mr=3)
+    got = host(lat.unpack(xg, nrhs))
+    for k in range(nrhs):
+        ref = sap.sap(op, f[k], x0[k], taus[k], block, 2, 3)
+        assert rel_err(got[k], ref) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 2e-5), ("bf16", 5e-2)])
+def test_sap_reduced_precision(prec, tol):
+    case("sap 8^4 " + prec)
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    qmg, lat, op = _op(dims, block)
+    f = random_spinors(dims, 1, seed_for(2, "b"))
+    xg = lat.field(1, prec)
+    fg = lat.pack(dev(f), prec)
+    lat.sap_smooth(xg, fg, [0.01], 1, nsweep=3, n_mr=3, prec=prec)
+    got = host(lat.unpack(xg, 1, prec))[0]
+    ref = sap.sap(op, host(lat.unpack(fg, 1, prec))[0], np.zeros_like(f[0]), 0.01, block, 3, 3)
+    assert rel_err(got, ref) < tol
+
+
+def _mg(dims, block, ntv=8, csw=1.0):
+    qmg, lat, op = _op(dims, block, csw)
+    W = random_test_vectors(dims, ntv, seed_for(2, "W"))
+    lat.set_test_vectors(lat.pack(dev(W)), ntv)
+    return qmg, lat, op, mg.TwoLevel(op, list(W), block), lat.coarse_site_order()
+
+
+@pytest.mark.parametrize("dims,block", [((8, 8, 8, 8), (4, 4, 4, 4)), ((4, 4, 4, 4), (2, 2, 2, 2))])
+def test_restrict_prolong_coarse_parity(dims, block):
+    case("restrict/prolong/coarse %s" % (dims,))
+    ntv = 8
+    qmg, lat, op, h, order = _mg(dims, block, ntv)
+    v = random_spinors(dims, 2, 31)
+    yc = host(lat.restrict(lat.coarse(2), lat.pack(dev(v)), 2)).view(np.complex128)
+    y = coarse_to_lex(yc, order, ntv)
+    for k in range(2):
+        assert rel_err(y[k], mg.restrict(h.P, v[k], block)) < 1e-13
+    rng = np.random.default_rng(4)
+    ylex = rng.standard_normal((2, len(order), 2 * ntv)) + 1j * rng.standard_normal((2, len(order), 2 * ntv))
+    yg = dev(lex_to_coarse(ylex, order).view(np.float64))
+    pv = host(lat.unpack(lat.prolong(lat.field(2), yg, 2), 2))
+    for k in range(2):
+        assert rel_err(pv[k], mg.prolong(h.P, ylex[k], dims, block)) < 1e-13
+    taus = [0.0, 0.3]
+    out = coarse_to_lex(host(lat.apply_coarse(lat.coarse(2), yg, taus, 2)).view(np.complex128), order, ntv)
+    for k in range(2):
+        assert rel_err(out[k], h.coarse.apply(ylex[k], taus[k])) < 1e-13
+
+
+def test_coarse_gmres_fixed_iterations():
+    case("coarse gmres 8^4 fixed 12 iterations")
+    ntv = 8
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    qmg, lat, op, h, order = _mg(dims, block, ntv)
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal((2, len(order), 2 * ntv)) + 1j * rng.standard_normal((2, len(order), 2 * ntv))
+    taus = [0.01, -0.05]
+    yg = lat.coarse_solve(lat.coarse(2), dev(lex_to_coarse(r, order).view(np.float64)), taus, 2, iters=12, tol=0.0)
+    y = coarse_to_lex(host(yg).view(np.complex128), order, ntv)
+    for k in range(2):
+        ref, its, _ = krylov.gmres(lambda v: h.coarse.apply(v, taus[k]), r[k], 12)
+        assert its == 12
+        assert rel_err(y[k], ref) < 1e-11
+
+
+def test_vcycle_parity():
+    case("vcycle 8^4 f64 fixed coarse iterations")
+    ntv = 8
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    qmg, lat, op, h, order = _mg(dims, block, ntv)
+    r = random_spinors(dims, 1, 41)
+    prm = qmg.default_params(coarse_maxiter=10, coarse_tol=0.0, nu_post=2, n_mr=3)
+    z = host(lat.unpack(lat.vcycle(lat.field(1), lat.pack(dev(r)), [0.02], 1, prm)))
+    ref = h.vcycle(r[0], 0.02, 2, 3, 10, None)
+    assert rel_err(z[0], ref) < 1e-11
+
+
+def test_rank_deficient_test_vectors_rejected():
+    case("rank deficient W")
+    qmg, lat, op = _op((8, 8, 8, 8), (4, 4, 4, 4))
+    W = random_test_vectors((8, 8, 8, 8), 4, 3)
+    W[3] = W[1] * (0.5 - 0.25j)
+    with pytest.raises(qmg.QmgError) as e:
+        lat.set_test_vectors(lat.pack(dev(W)), 4)
+    assert e.value.status == -5

@@ -21,7 +21,7 @@ def test_gamma_basis():
         for nu in range(4):
             ac = GAMMA[mu] @ GAMMA[nu] + GAMMA[nu] @ GAMMA[mu]
             assert np.allclose(ac, 2.0 * (mu == nu) * I4)
-        # gamma5 anticommutes with every gamma_mu (text before eq. (2.4))
+        # gamma5 anticommutes with every gamma_mu (eq. (2.4))
         assert np.allclose(GAMMA5 @ GAMMA[mu], -GAMMA[mu] @ GAMMA5)
     assert np.allclose(GAMMA5, np.diag([1, 1, -1, -1]))
     # sigma_{mu nu} is block diagonal in chirality, so the clover term splits into 6x6 blocks
@@ -113,7 +113,7 @@ def test_dense_brute_force_2x4():
 
 
 def test_gamma5_hermiticity():
-    """eq. (2.6): Gamma5 D = (Gamma5 D)^H, i.e. <phi, Q psi> = <Q phi, psi>."""
+    """eq. (2.7): Gamma5 D = (Gamma5 D)^H, i.e. <phi, Q psi> = <Q phi, psi>."""
     dims = (4, 4, 4, 4)
     U = random_links(dims, 0.5, seed_for(2, "U"))
     C = clover.clover_term(U, 1.0)

@@ -181,7 +181,7 @@ def test_P_orthonormal_spin_preserving_and_spans_W():
     P = h.P
     G = np.einsum("bhki,bhkj->bhij", np.conj(P), P)
     assert np.abs(G - np.eye(P.shape[-1])).max() < 1e-14
-    # Gamma5 P = P Gamma5^c (eq. (2.7))
+    # Gamma5 P = P Gamma5^c (text before eq. (2.9))
     y = random_spinors((1, 1, 1, 1), 1, 9)[0].reshape(-1)[:1] * np.ones((P.shape[0], 2 * P.shape[-1]))
     y = y + 0.3j * np.arange(y.size).reshape(y.shape)
     lhs = dirac.gamma5(mg.prolong(P, y, dims, block))
@@ -215,14 +215,14 @@ def test_coarse_operator_equals_dense_galerkin(dims, block):
             ref[b * nc:(b + 1) * nc, bb * nc:(bb + 1) * nc] += Dc[b, d]
     assert np.abs(ref - Dcd).max() < 1e-13 * np.abs(Dcd).max()
     assert V * 12 == Pd.shape[0]
-    # Q_c = Gamma5^c D_c is Hermitian (eq. (2.7))
+    # Q_c = Gamma5^c D_c is Hermitian (text before eq. (2.9))
     g5c = np.kron(np.eye(nbt), np.diag([1.0] * (nc // 2) + [-1.0] * (nc // 2)))
     Qc = g5c @ ref
     assert np.abs(Qc - Qc.conj().T).max() < 1e-13
 
 
-def test_coarse_grid_identity_eq27():
-    """eq. (2.7): I - P Q_c^{-1} P^H Q = I - P D_c^{-1} P^H D."""
+def test_coarse_grid_identity_eq29():
+    """eq. (2.9): I - P Q_c^{-1} P^H Q = I - P D_c^{-1} P^H D."""
     dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
     op, W, h = _small_mg(dims, block, ntv=4)
     Pd = _dense_P(h.P, dims, block)
