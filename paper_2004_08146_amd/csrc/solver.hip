@@ -14,6 +14,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 #include "qmg_ctx.h"
@@ -109,7 +110,10 @@ struct Space {
     qmg_status st = dots(d, w, 1, 0, w);
     if (st != QMG_OK) return st;
     out.resize(nrhs);
-    for (int k = 0; k < nrhs; ++k) out[k] = std::sqrt(std::max(0.0, d[k].real()));
+    for (int k = 0; k < nrhs; ++k) {
+      const double v = d[k].real();  // NaN/Inf must survive to the callers' checks
+      out[k] = std::isfinite(v) ? std::sqrt(std::max(0.0, v)) : std::numeric_limits<double>::quiet_NaN();
+    }
     return QMG_OK;
   }
   // w_k += sum_j coef[k*J + j] V_j,k

@@ -7,5 +7,5 @@ sides of every parity comparison receive identical bits.
 """
 from .fields import (  # noqa: F401
     seed_for, random_links, unit_links, random_spinors, gauge_transform,
-    random_test_vectors, kappa_to_m0,
+    random_test_vectors, kappa_to_m0, device_gaussian_spinors,
 )

@@ -38,7 +38,7 @@ def _random_su3(rng, n, eps):
     h = h - tr[:, None, None] * np.eye(3)
     w, v = np.linalg.eigh(h)
     ph = np.exp(1j * eps * w)
-    return np.einsum("nab,nb,ncb->nac", v, ph, np.conj(v))
+    return (v * ph[:, None, :]) @ np.conj(np.swapaxes(v, -1, -2))
 
 
 def random_links(dims, eps, seed, chunk=1 << 20):
@@ -81,3 +81,15 @@ def gauge_transform(dims, seed):
 def random_test_vectors(dims, ntv, seed):
     """``ntv`` complex Gaussian fields used as multigrid test vectors."""
     return random_spinors(dims, ntv, seed)
+
+
+def device_gaussian_spinors(dims, nrhs, seed, device="cuda"):
+    """Complex Gaussian spinor fields drawn on the GPU with torch's seeded
+    generator (for large inputs only the GPU consumes, e.g. setup vectors)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    shape = (int(nrhs),) + tuple(int(d) for d in dims) + (4, 3)
+    re = torch.randn(shape, generator=g, device=device, dtype=torch.float64)
+    im = torch.randn(shape, generator=g, device=device, dtype=torch.float64)
+    return torch.complex(re, im)

@@ -39,3 +39,16 @@ def coarse_to_lex(yc_gpu, order, ntv):
 
 def lex_to_coarse(y_lex, order):
     return np.ascontiguousarray(y_lex[..., order, :])
+
+
+_BIG = {}
+
+
+def big_inputs(dims, eps, cfg, nrhs):
+    """Links and spinors of a large lattice, generated once per process."""
+    from synth import random_links, random_spinors, seed_for
+    key = (dims, eps, cfg)
+    if key not in _BIG:
+        _BIG.clear()
+        _BIG[key] = random_links(dims, eps, seed_for(cfg, "U"))
+    return _BIG[key], random_spinors(dims, nrhs, seed_for(cfg, "b"))

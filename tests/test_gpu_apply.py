@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from gpu_common import case, dev, host, need_gpu, torch
+from gpu_common import big_inputs, case, dev, host, need_gpu, torch
 from helpers import oracle_at_sites, rel_err, sample_sites
 from oracle import clover as oclover
 from oracle import dirac
@@ -107,11 +107,10 @@ def test_apply_full_size_sampled(prec, nrhs, tol):
     case("apply 64x32^3 sampled %s nrhs=%d" % (prec, nrhs))
     qmg = need_gpu()
     dims = (64, 32, 32, 32)
-    U = random_links(dims, 0.5, seed_for(5, "U"))
+    U, psi = big_inputs(dims, 0.5, 5, nrhs)
     m0 = -0.8
     lat = qmg.Lattice(dims, (4, 4, 4, 4))
     lat.set_gauge(dev(U), m0, 1.0)
-    psi = random_spinors(dims, nrhs, seed_for(5, "b"))
     taus = [0.0025 * (2 * k - 15) for k in range(nrhs)]
     fin = lat.pack(dev(psi), prec)
     out = lat.unpack(lat.apply_Q_shifted(lat.field(nrhs, prec), fin, taus, nrhs, prec), nrhs, prec)

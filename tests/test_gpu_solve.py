@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from gpu_common import case, dev, host, need_gpu, torch
+from gpu_common import big_inputs, case, dev, host, need_gpu, torch
 from helpers import oracle_at_sites, sample_sites
 from oracle import clover as oclover
 from oracle import dirac
@@ -109,11 +109,10 @@ def test_solve_full_size_sampled():
     case("solve 64x32^3 sampled")
     qmg = need_gpu()
     dims = (64, 32, 32, 32)
-    U = random_links(dims, 0.5, seed_for(5, "U"))
+    U, b = big_inputs(dims, 0.5, 5, 2)
     m0, csw = -0.8, 1.0
     lat = qmg.Lattice(dims, (4, 4, 4, 4))
     lat.set_gauge(dev(U), m0, csw)
-    b = random_spinors(dims, 2, seed_for(5, "b"))
     taus = [0.01, -0.02]
     bg = lat.pack(dev(b))
     x = lat.field(2)
