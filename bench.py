@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--restart", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the extra FP64/BF16 solves")
+    ap.add_argument("--tune-cache", type=str, default=None, help="autotuner JSON cache (default: fresh)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -136,6 +137,11 @@ def main():
 
     lat = qmg.Lattice(dims, (4, 4, 4, 4))
     lat.set_gauge(torch.from_numpy(U).cuda(), m0, csw)
+    tune_path = args.tune_cache or os.path.join("/tmp", "qmg_tune_%d.json" % os.getpid())
+    t0 = time.time()
+    lat.autotune(tune_path)
+    tuning = json.load(open(tune_path))
+    print("[bench] autotune %.1f s: %s" % (time.time() - t0, json.dumps(tuning)), file=sys.stderr, flush=True)
     bg = lat.pack(torch.from_numpy(b).cuda())
     ntv = 24
     W0 = lat.pack(device_gaussian_spinors(dims, ntv, seed_for(5, "W")))
@@ -227,6 +233,7 @@ def main():
         "q_apply": qapply,
         "sap_sweep_f32": {"ms": sap_ms, "gbps": sap_bytes / sap_ms / 1e6, "hbm_frac": sap_bytes / sap_ms / 1e6 / HBM_PEAK_GBS},
         "roofline": roofline,
+        "autotune": tuning,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -178,8 +178,11 @@ qmg_status qmg_create(qmg_ctx** out, const int dims[4], const int block[4], int 
         c->h_nbr[b * 8 + 2 * mu + dir] = id_of_lex[lex];
       }
   }
+  std::vector<int> lexord(id_of_lex);
   if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->d_nbr, sizeof(int) * nb * 8) != hipSuccess ||
       hipMalloc(&c->d_bcoord, sizeof(int) * nb * 4) != hipSuccess ||
+      hipMalloc(&c->d_lexord, sizeof(int) * nb) != hipSuccess ||
+      hipMemcpy(c->d_lexord, lexord.data(), sizeof(int) * nb, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_nbr, c->h_nbr.data(), sizeof(int) * nb * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_bcoord, c->h_bcoord.data(), sizeof(int) * nb * 4, hipMemcpyHostToDevice) != hipSuccess) {
     qmg_destroy(c);
@@ -187,6 +190,7 @@ qmg_status qmg_create(qmg_ctx** out, const int dims[4], const int block[4], int 
   }
   g.nbr = c->d_nbr;
   g.bcoord = c->d_bcoord;
+  g.lexord = c->d_lexord;
   *out = c;
   return QMG_OK;
 }
@@ -203,6 +207,7 @@ qmg_status qmg_destroy(qmg_ctx* c) {
   for (auto& kv : c->ws) hipFree(kv.second.first);
   if (c->d_nbr) hipFree(c->d_nbr);
   if (c->d_bcoord) hipFree(c->d_bcoord);
+  if (c->d_lexord) hipFree(c->d_lexord);
   delete c;
   return QMG_OK;
 }

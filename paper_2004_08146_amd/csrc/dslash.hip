@@ -101,6 +101,132 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a) {
   store_spinor(out, g, b, l, o);
 }
 
+// ---- 4^4 blocks: compile-time geometry, 32-bit offsets, R right-hand sides per
+// thread sharing every link load.  One work-group = one block x R rhs.
+template <int MU> struct Sh44 { static constexpr int v = 6 - 2 * MU; };
+
+template <typename C, typename P>
+__device__ __forceinline__ Spinor<C> ld_spinor44(const P* f, uint32_t b, uint32_t l) {
+  Spinor<C> p;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      auto v = cv(ldo(f, ((b * 12u + (uint32_t)(3 * s + c)) << 8) + l));
+      p.s[s][c] = cpx<C>{C(v.re), C(v.im)};
+    }
+  return p;
+}
+template <typename C, typename P>
+__device__ __forceinline__ Link<C> ld_link44(const P* U, uint32_t b, int mu, uint32_t l) {
+  Link<C> u;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      auto v = cv(ldo(U, ((b * 36u + (uint32_t)(mu * 9 + 3 * a + c)) << 8) + l));
+      u.u[a][c] = cpx<C>{C(v.re), C(v.im)};
+    }
+  return u;
+}
+
+// one hop (HOP = 2 mu for x + mu, 2 mu + 1 for x - mu) for R right-hand sides
+template <typename C, int HOP, int R, typename P>
+__device__ __forceinline__ void hop44(Spinor<C> (&acc)[R], const P* const (&in)[R], const P* U, const int* nbr,
+                                      uint32_t b, uint32_t l, int nr) {
+  constexpr int MU = HOP / 2;
+  constexpr bool FWD = (HOP % 2) == 0;
+  constexpr int SH = Sh44<MU>::v;
+  const uint32_t lc = (l >> SH) & 3u;
+  const uint32_t bo = (uint32_t)nbr[b * 8 + HOP];
+  uint32_t bn, ln;
+  if (FWD) {
+    bn = lc < 3u ? b : bo;
+    ln = lc < 3u ? l + (1u << SH) : l - (3u << SH);
+  } else {
+    bn = lc > 0u ? b : bo;
+    ln = lc > 0u ? l - (1u << SH) : l + (3u << SH);
+  }
+  const Link<C> u = FWD ? ld_link44<C>(U, b, MU, l) : ld_link44<C>(U, bn, MU, ln);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r < nr) {
+      const Half<C> h = project(ld_spinor44<C>(in[r], bn, ln), MU, FWD);
+      accum_recon(acc[r], FWD ? umul(u, h) : udagmul(u, h), MU, FWD);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <typename S, bool CLOVER, int MODE, int R, int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1))) void k_dslash44(DsArgs<S> a) {
+  using C = typename PT<S>::real;
+  using P = typename PT<S>::stor;
+  const int w = blockIdx.x, nw = gridDim.x;
+  const int L = (a.remap && (nw & 7) == 0) ? (w & 7) * (nw >> 3) + (w >> 3) : w;
+  const int ng = (a.nrhs + R - 1) / R;
+  const int k0 = (L % ng) * R;
+  // blocks are visited in lexicographic order so that neighbouring blocks run
+  // close together in time (and, with the XCD remap, on the same XCD)
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(a.g.lexord[L / ng]);
+  const uint32_t l = threadIdx.x;
+  const int nr = a.nrhs - k0 < R ? a.nrhs - k0 : R;
+  const P* in[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) in[r] = a.in + (size_t)(k0 + (r < nr ? r : 0)) * a.fstride;
+  Spinor<C> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[r].s[s][c] = czero<C>();
+#pragma unroll 1
+  for (int hop = 0; hop < 8; ++hop) {
+    switch (hop) {
+      case 0: hop44<C, 0, R>(acc, in, a.U, a.g.nbr, b, l, nr); break;
+      case 1: hop44<C, 1, R>(acc, in, a.U, a.g.nbr, b, l, nr); break;
+      case 2: hop44<C, 2, R>(acc, in, a.U, a.g.nbr, b, l, nr); break;
+      case 3: hop44<C, 3, R>(acc, in, a.U, a.g.nbr, b, l, nr); break;
+      case 4: hop44<C, 4, R>(acc, in, a.U, a.g.nbr, b, l, nr); break;
+      case 5: hop44<C, 5, R>(acc, in, a.U, a.g.nbr, b, l, nr); break;
+      case 6: hop44<C, 6, R>(acc, in, a.U, a.g.nbr, b, l, nr); break;
+      default: hop44<C, 7, R>(acc, in, a.U, a.g.nbr, b, l, nr); break;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r >= nr) break;
+    const Spinor<C> self = ld_spinor44<C>(in[r], b, l);
+    Spinor<C> o;
+    if (CLOVER) {
+      o = apply_diag<C>(a.diag, a.g, (int)b, (int)l, self);
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o.s[s][c] = C(a.mass4) * self.s[s][c];
+    }
+    const C tau = C(a.tau[k0 + r]);
+    P* out = a.out + (size_t)(k0 + r) * a.fstride;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cpx<C> v = o.s[s][c] - C(0.5) * acc[r].s[s][c];
+        if (MODE == 0) v = (s < 2) ? v - tau * self.s[s][c] : v + tau * self.s[s][c];
+        else v = (s < 2) ? v - tau * self.s[s][c] : -v - tau * self.s[s][c];
+        sto(out, ((b * 12u + (uint32_t)(3 * s + c)) << 8) + l, vc(v, (P*)nullptr));
+      }
+  }
+}
+
+template <typename S, bool CLOVER, int MODE, int R, int W>
+void launch44(const DsArgs<S>& a, int nb, hipStream_t s) {
+  const unsigned ng = (unsigned)((a.nrhs + R - 1) / R);
+  hipLaunchKernelGGL((k_dslash44<S, CLOVER, MODE, R, W>), dim3((unsigned)nb * ng), dim3(256), 0, s, a);
+}
+
 template <typename S, bool CLOVER, int MODE>
 void launch_t(const qmg_ctx* c, void* out, const void* in, const double* tau, int nrhs, hipStream_t s,
               int p) {
@@ -116,6 +242,20 @@ void launch_t(const qmg_ctx* c, void* out, const void* in, const double* tau, in
   a.remap = c->tune.dslash_xcd_remap;
   a.g = c->g;
   for (int i = 0; i < QMG_MAXRHS; ++i) a.tau[i] = i < nrhs ? tau[i] : 0.0;
+  const bool b44 = c->g.block[0] == 4 && c->g.block[1] == 4 && c->g.block[2] == 4 && c->g.block[3] == 4;
+  const int var = c->tune.force_variant >= 0 ? c->tune.force_variant : c->tune.dslash[p][nrhs == 1 ? 0 : 1];
+  if (b44 && var > 0 && var < kNumDsVariants) {
+    switch (var) {
+      case 1: launch44<S, CLOVER, MODE, 1, 0>(a, c->g.nb, s); break;
+      case 2: launch44<S, CLOVER, MODE, 1, 2>(a, c->g.nb, s); break;
+      case 3: launch44<S, CLOVER, MODE, 1, 3>(a, c->g.nb, s); break;
+      case 4: launch44<S, CLOVER, MODE, 1, 4>(a, c->g.nb, s); break;
+      case 5: launch44<S, CLOVER, MODE, 2, 0>(a, c->g.nb, s); break;
+      case 6: launch44<S, CLOVER, MODE, 2, 2>(a, c->g.nb, s); break;
+      default: launch44<S, CLOVER, MODE, 4, 0>(a, c->g.nb, s); break;
+    }
+    return;
+  }
   const int wg = 256;
   unsigned nwg = (unsigned)((c->g.V + wg - 1) / wg) * (unsigned)nrhs;
   if ((1 << c->g.bs_log) >= wg)

@@ -15,11 +15,19 @@ inline size_t cbytes(int p) { return p == QMG_F64 ? 16 : (p == QMG_F32 ? 8 : 4);
 // coarse vectors are double for F64 and float otherwise
 inline int coarse_prec(int p) { return p == QMG_F64 ? QMG_F64 : QMG_F32; }
 
+// Stencil launch variants for 4^4 blocks: R right-hand sides per thread and a
+// waves-per-SIMD occupancy target W (0: compiler's choice).  Variant 0 is the
+// generic kernel (any block shape).
+struct DsVariant { int R, W; };
+constexpr DsVariant kDsVariants[] = {{0, 0}, {1, 0}, {1, 2}, {1, 3}, {1, 4}, {2, 0}, {2, 2}, {4, 0}};
+constexpr int kNumDsVariants = 8;
+
 struct Tune {
-  int dslash_wg = 256;       // work-group size of the stencil
-  int dslash_xcd_remap = 1;  // XCD-aware mapping of work-groups to blocks
-  int sap_variant = 0;
-  int coarse_rhs_tile = 4;   // right-hand sides per coarse-apply work-group
+  int dslash[3][2] = {{1, 1}, {1, 1}, {1, 1}};  // [prec][nrhs == 1 ? 0 : 1] -> variant index
+  int dslash_xcd_remap = 1;                      // XCD-aware mapping of work-groups to blocks
+  int force_variant = -1;                        // >= 0: use this stencil variant (tuning, tests)
+  int coarse_rhs_tile = 4;                       // right-hand sides per coarse-apply work-group
+  bool tuned = false;
 };
 
 struct qmg_ctx {
@@ -27,6 +35,7 @@ struct qmg_ctx {
   Geom g{};                    // device pointers for tables inside
   int* d_nbr = nullptr;
   int* d_bcoord = nullptr;
+  int* d_lexord = nullptr;
   std::vector<int> h_nbr, h_bcoord;
   std::vector<int64_t> lex_of_block;
   bool sap_ok = false;

@@ -70,6 +70,21 @@ template <typename P, typename R> QMG_HD void stcv(P* p, int64_t i, cpx<R> a) {
   stc(p, i, cpx<T>{T(a.re), T(a.im)});
 }
 
+// load / store with a 32-bit element offset from a uniform base pointer (the
+// compiler then addresses with an SGPR base and one VGPR offset)
+template <typename P> QMG_HD P ldo(const P* base, uint32_t elem) {
+  return *reinterpret_cast<const P*>(reinterpret_cast<const char*>(base) + (size_t)(elem * (uint32_t)sizeof(P)));
+}
+template <typename P> QMG_HD void sto(P* base, uint32_t elem, P v) {
+  *reinterpret_cast<P*>(reinterpret_cast<char*>(base) + (size_t)(elem * (uint32_t)sizeof(P))) = v;
+}
+QMG_HD cpx<double> cv(double2 v) { return {v.x, v.y}; }
+QMG_HD cpx<float> cv(float2 v) { return {v.x, v.y}; }
+QMG_HD cpx<float> cv(uint32_t v) { return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)}; }
+QMG_HD double2 vc(cpx<double> a, double2*) { return make_double2(a.re, a.im); }
+QMG_HD float2 vc(cpx<float> a, float2*) { return make_float2(a.re, a.im); }
+QMG_HD uint32_t vc(cpx<float> a, uint32_t*) { return f32_to_bf16_bits(a.re) | (f32_to_bf16_bits(a.im) << 16); }
+
 // ------------------------------------------------------------------ layout --
 // Sites are grouped in blocks of B0 x B1 x B2 x B3 (powers of two), numbered
 // colour-major (all red blocks, then all black blocks).  A site is (b, l) with
@@ -90,6 +105,7 @@ struct Geom {
   int64_t V;
   const int* nbr;     // [nb][8] neighbour block: 2*mu forward, 2*mu+1 backward
   const int* bcoord;  // [nb][4] block coordinates
+  const int* lexord;  // [nb] block id of the i-th block in lexicographic order
 };
 
 QMG_HD int loc(const Geom& g, int l, int mu) { return (l >> g.sh[mu]) & g.msk[mu]; }

@@ -1,9 +1,126 @@
-// Launch-variant autotuner: times the variants of the hot kernels on this
-// context's shape and keeps the fastest.
+// Launch-variant autotuner.
+//
+// For the context's lattice and block shape it times every stencil variant
+// (generic kernel; 4^4-block kernels with 1, 2 or 4 right-hand sides per
+// thread and occupancy targets) in FP64 / FP32 / BF16 for one and for sixteen
+// right-hand sides, and keeps the fastest per (precision, batch class).  The
+// choice is cached in a JSON file keyed by GPU architecture, lattice, block
+// and clover flag; an existing entry is reused without timing (this is also
+// how a caller pins a variant).
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "qmg_ctx.h"
 
+namespace {
+
+std::string tune_key(const qmg_ctx* c) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s|%dx%dx%dx%d|%dx%dx%dx%d|clover=%d", arch.c_str(), c->g.dims[0], c->g.dims[1],
+                c->g.dims[2], c->g.dims[3], c->g.block[0], c->g.block[1], c->g.block[2], c->g.block[3],
+                c->clover ? 1 : 0);
+  return buf;
+}
+
+const char* kPrecName[3] = {"f64", "f32", "bf16"};
+
+// Reads "<key>|dslash|<prec>|<cls>": <variant> entries of our own cache file.
+bool load_cache(qmg_ctx* c, const std::string& path, const std::string& key) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string txt = ss.str();
+  int found = 0;
+  for (int p = 0; p < 3; ++p)
+    for (int cls = 0; cls < 2; ++cls) {
+      const std::string k = "\"" + key + "|dslash|" + kPrecName[p] + "|" + std::to_string(cls) + "\":";
+      const size_t pos = txt.find(k);
+      if (pos == std::string::npos) continue;
+      int v = -1;
+      if (std::sscanf(txt.c_str() + pos + k.size(), " %d", &v) == 1 && v >= 0 && v < kNumDsVariants) {
+        c->tune.dslash[p][cls] = v;
+        ++found;
+      }
+    }
+  return found == 6;
+}
+
+}  // namespace
+
 qmg_status tune_run(qmg_ctx* c, const char* path) {
-  (void)path;
-  c->tune = Tune{};
+  const std::string key = tune_key(c);
+  if (path && load_cache(c, path, key)) {
+    c->tune.tuned = true;
+    return QMG_OK;
+  }
+  const bool b44 = c->g.block[0] == 4 && c->g.block[1] == 4 && c->g.block[2] == 4 && c->g.block[3] == 4;
+  hipStream_t s = nullptr;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return set_err(c, QMG_E_HIP, "autotune: event creation failed");
+  std::vector<double> tau(QMG_MAXRHS, 0.0);
+  std::ostringstream js;
+  js << "{\n";
+  bool first = true;
+  qmg_status st = QMG_OK;
+  for (int p = 0; p < 3 && st == QMG_OK; ++p)
+    for (int cls = 0; cls < 2 && st == QMG_OK; ++cls) {
+      const int n = cls == 0 ? 1 : 16;
+      const size_t bytes = field_elems(c) * cbytes(p) * n;
+      void* in = ws_get(c, "tune_in", bytes);
+      void* out = ws_get(c, "tune_out", bytes);
+      if (!in || !out) { st = set_err(c, QMG_E_NOMEM, "autotune: out of device memory"); break; }
+      if (launch_fill_zero(in, bytes, s) != hipSuccess) { st = set_err(c, QMG_E_HIP, "autotune: fill"); break; }
+      double best_ms = 1e30;
+      int best = c->tune.dslash[p][cls];
+      std::ostringstream times;
+      for (int v = 0; v < kNumDsVariants; ++v) {
+        if (v > 0 && !b44) break;
+        c->tune.force_variant = v;
+        hipError_t e = launch_dslash(c, p, out, in, tau.data(), n, 1, s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        const int reps = 5;
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_dslash(c, p, out, in, tau.data(), n, 1, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { st = hip_err(c, e, "autotune"); break; }
+        ms /= reps;
+        times << (v ? ", " : "") << ms;
+        if (ms < best_ms) { best_ms = ms; best = v; }
+      }
+      c->tune.force_variant = -1;
+      if (st != QMG_OK) break;
+      c->tune.dslash[p][cls] = best;
+      js << (first ? "" : ",\n") << "  \"" << key << "|dslash|" << kPrecName[p] << "|" << cls << "\": " << best
+         << ",\n  \"" << key << "|dslash|" << kPrecName[p] << "|" << cls << "|ms\": [" << times.str() << "]";
+      first = false;
+    }
+  js << "\n}\n";
+  c->tune.force_variant = -1;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  ws_release(c, "tune_in");
+  ws_release(c, "tune_out");
+  if (st != QMG_OK) return st;
+  c->tune.tuned = true;
+  if (path) {
+    std::ofstream f(path);
+    if (!f) return set_err(c, QMG_E_ARG, std::string("autotune: cannot write ") + path);
+    f << js.str();
+  }
   return QMG_OK;
 }

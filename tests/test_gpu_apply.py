@@ -120,3 +120,33 @@ def test_apply_full_size_sampled(prec, nrhs, tol):
         ref = oracle_at_sites(U, host(pin[k]), m0, 1.0, sites, taus[k])
         got = np.array([host(out[k][x]) for x in sites])
         assert rel_err(got, ref) < tol
+
+
+def _force_variant(lat, tmp_path, dims, block, clover, v):
+    key = "gfx950|%s|%s|clover=%d" % ("x".join(map(str, dims)), "x".join(map(str, block)), clover)
+    entries = ['"%s|dslash|%s|%d": %d' % (key, p, c, v) for p in ("f64", "f32", "bf16") for c in (0, 1)]
+    path = tmp_path / ("tune_%d.json" % v)
+    path.write_text("{\n" + ",\n".join(entries) + "\n}\n")
+    lat.autotune(str(path))
+
+
+@pytest.mark.parametrize("variant", range(8))
+def test_stencil_variants(variant, tmp_path):
+    """Every launch variant of the stencil (generic, 4^4 kernels with 1/2/4 rhs per
+    thread and occupancy targets) against the oracle, with a ragged rhs batch."""
+    case("stencil variant %d" % variant)
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    qmg, lat, U, psi = _setup(dims, block, 0.5, -0.8, 1.0, 2, 3)
+    _force_variant(lat, tmp_path, dims, block, 1, variant)
+    C = oclover.clover_term(U, 1.0)
+    taus = [0.01, -0.2, 0.05]
+    for prec, tol in (("f64", 1e-13), ("f32", 1e-6)):
+        fin = lat.pack(dev(psi), prec)
+        pin = host(lat.unpack(fin, 3, prec))
+        for nrhs in (1, 3):
+            outQ = host(lat.unpack(lat.apply_Q_shifted(lat.field(nrhs, prec), fin, taus[:nrhs], nrhs, prec),
+                                   nrhs, prec))
+            outA = host(lat.unpack(lat.apply_A(lat.field(nrhs, prec), fin, taus[:nrhs], nrhs, prec), nrhs, prec))
+            for k in range(nrhs):
+                assert rel_err(outQ[k], dirac.apply_Q_shifted(U, pin[k], -0.8, taus[k], C)) < tol
+                assert rel_err(outA[k], dirac.apply_A(U, pin[k], -0.8, taus[k], C)) < tol
