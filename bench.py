@@ -100,6 +100,46 @@ def cpu_baseline(U, b0, m0, csw, tau, applies_per_rhs):
     }
 
 
+def kernels_mode(args, dims, torch, qmg, unit_links):
+    """A few launches of each hot kernel (memory traffic does not depend on the
+    field values, so unit links are used) plus a plain 1 GiB device copy whose
+    known size calibrates the HBM byte counters."""
+    V = int(np.prod(dims))
+    nrhs = args.nrhs
+    lat = qmg.Lattice(dims, (4, 4, 4, 4))
+    lat.set_gauge(torch.from_numpy(unit_links(dims)).cuda(), args.m0, 1.0)
+    if args.tune_cache:
+        lat.autotune(args.tune_cache)
+    timer = EventTimer(torch)
+    taus = [0.0] * nrhs
+    out = {}
+    for prec, n in (("f64", 1), ("f32", nrhs)):
+        a = lat.field(n, prec)
+        o = lat.field(n, prec)
+        ms = timer(lambda: lat.apply_Q_shifted(o, a, taus[:n], n, prec), 3)
+        byts = apply_bytes_per_site(prec, n, True) * V
+        out["apply_%s_%d" % (prec, n)] = {"ms": ms, "alg_bytes": byts, "gbps": byts / ms / 1e6}
+        del a, o
+    xs = lat.field(nrhs, "f32")
+    fs = lat.field(nrhs, "f32")
+    ms = timer(lambda: lat.sap_smooth(xs, fs, taus, nrhs, 1, 3, "f32"), 2)
+    out["sap_f32_%d" % nrhs] = {"ms": ms, "alg_bytes": sap_bytes_per_site("f32", nrhs, True) * V}
+    del xs, fs
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    ms = timer(lambda: dst.copy_(src), 3)
+    out["copy_1GiB"] = {"ms": ms, "bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                        "gbps": 2 * (1 << 30) / ms / 1e6}
+    # the library's own streaming kernels on 1 GiB fields: read-only (dot) and copy
+    nf = (1 << 30) // lat.field_bytes("f64")
+    fa = lat.field(nf, "f64")
+    fb = lat.field(nf, "f64")
+    ms = timer(lambda: lat.field_dot(fa, fa, nf, "f64"), 3)
+    out["dot_1GiB_read"] = {"ms": ms, "gbps": nf * lat.field_bytes("f64") / ms / 1e6}
+    del fa, fb
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +153,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the extra FP64/BF16 solves")
     ap.add_argument("--tune-cache", type=str, default=None, help="autotuner JSON cache (default: fresh)")
+    ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",
+                    help="kernels: only a few launches of the hot kernels and a 1 GiB copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -121,9 +163,11 @@ def main():
 
     import torch
     from paper_2004_08146_amd import qmg
-    from synth import device_gaussian_spinors, random_links, random_spinors, seed_for
+    from synth import device_gaussian_spinors, random_links, random_spinors, seed_for, unit_links
 
     dims = tuple(int(v) for v in args.dims.split(","))
+    if args.mode == "kernels":
+        return kernels_mode(args, dims, torch, qmg, unit_links)
     V = int(np.prod(dims))
     nrhs = args.nrhs
     csw, m0 = 1.0, args.m0

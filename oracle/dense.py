@@ -50,3 +50,40 @@ def dense_gamma5(V):
 def dense_Q(U, m0, clover=None):
     V = int(np.prod(U.shape[:4]))
     return dense_gamma5(V) @ dense_D(U, m0, clover)
+
+
+def sparse_D(U, m0, clover=None):
+    """D as a scipy.sparse CSR matrix, from the same site couplings (any size)."""
+    import scipy.sparse as sp
+    dims = U.shape[:4]
+    V = int(np.prod(dims))
+    rows, cols, vals = [], [], []
+    base = np.arange(12)
+    for x in np.ndindex(*dims):
+        i = site_index(x, dims)
+        blk = (m0 + 4.0) * np.eye(12, dtype=np.complex128)
+        if clover is not None:
+            blk = blk + clover[x]
+        blocks = [(i, blk)]
+        for mu in range(4):
+            xp = list(x)
+            xp[mu] = (xp[mu] + 1) % dims[mu]
+            xm = list(x)
+            xm[mu] = (xm[mu] - 1) % dims[mu]
+            blocks.append((site_index(xp, dims), -0.5 * np.kron(I4 - GAMMA[mu], U[x][mu])))
+            blocks.append((site_index(xm, dims),
+                           -0.5 * np.kron(I4 + GAMMA[mu], np.conj(U[tuple(xm)][mu]).T)))
+        for j, b in blocks:
+            rows.append(np.repeat(12 * i + base, 12))
+            cols.append(np.tile(12 * j + base, 12))
+            vals.append(b.reshape(-1))
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(12 * V, 12 * V))
+    return A.tocsr()   # duplicate (i, j) entries are summed
+
+
+def sparse_Q(U, m0, clover=None):
+    import scipy.sparse as sp
+    V = int(np.prod(U.shape[:4]))
+    g5 = sp.diags(np.tile(np.repeat([1.0, 1.0, -1.0, -1.0], 3), V))
+    return (g5 @ sparse_D(U, m0, clover)).tocsr()

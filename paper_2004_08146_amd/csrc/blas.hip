@@ -16,7 +16,7 @@ constexpr int64_t kChunk = (int64_t)kDotWG * kDotPerThread;
 template <typename S>
 __global__ __launch_bounds__(kDotWG) void k_dot_stage1(double* partial, const typename PT<S>::stor* V, int64_t vstride,
                                                       int J, const typename PT<S>::stor* w, int64_t n,
-                                                      int64_t stride, int nchunk) {
+                                                      int64_t stride, int nchunk, int with_self) {
   __shared__ double red[2 * (kDotWG / 64)];
   const int chunk = blockIdx.x, k = blockIdx.y;
   const int64_t i0 = chunk * kChunk + threadIdx.x;
@@ -41,10 +41,53 @@ __global__ __launch_bounds__(kDotWG) void k_dot_stage1(double* partial, const ty
     }
     wg_sum<double, 2>(acc, red);
     if (threadIdx.x == 0) {
-      double* o = partial + (((int64_t)k * J + j) * nchunk + chunk) * 2;
+      double* o = partial + (((int64_t)k * (J + with_self) + j) * nchunk + chunk) * 2;
       o[0] = acc[0];
       o[1] = acc[1];
     }
+  }
+  if (with_self) {
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < kDotPerThread; ++t) acc[0] += norm2(wl[t]);
+    wg_sum<double, 2>(acc, red);
+    if (threadIdx.x == 0) {
+      double* o = partial + (((int64_t)k * (J + 1) + J) * nchunk + chunk) * 2;
+      o[0] = acc[0];
+      o[1] = 0.0;
+    }
+  }
+}
+
+// w_k += sum_j coef[k*J+j] V_j,k over one chunk, and partial[k][chunk] = ||new w_k||^2 there
+template <typename S>
+__global__ __launch_bounds__(kDotWG) void k_axpy_norm(typename PT<S>::stor* w, const typename PT<S>::stor* V,
+                                                     int64_t vstride, int J, const double* coef, int64_t n,
+                                                     int64_t stride, int nchunk, double* partial) {
+  using R = typename PT<S>::real;
+  __shared__ double red[2 * (kDotWG / 64)];
+  const int chunk = blockIdx.x, k = blockIdx.y;
+  const int64_t i0 = chunk * kChunk + threadIdx.x;
+  auto* wk = w + k * stride;
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < kDotPerThread; ++t) {
+    const int64_t i = i0 + (int64_t)t * kDotWG;
+    if (i < n) {
+      cpx<double> v = ldcv<double>(wk, i);
+      for (int j = 0; j < J; ++j) {
+        const cpx<double> c = {coef[((int64_t)k * J + j) * 2], coef[((int64_t)k * J + j) * 2 + 1]};
+        v = v + c * ldcv<double>(V + j * vstride + k * stride, i);
+      }
+      const cpx<R> vr = {R(v.re), R(v.im)};
+      stcv(wk, i, vr);
+      acc[0] += norm2(ldcv<double>(wk, i));
+    }
+  }
+  wg_sum<double, 2>(acc, red);
+  if (threadIdx.x == 0) {
+    partial[((int64_t)k * nchunk + chunk) * 2] = acc[0];
+    partial[((int64_t)k * nchunk + chunk) * 2 + 1] = 0.0;
   }
 }
 
@@ -138,21 +181,35 @@ void by_prec(int p, F&& f) {
 }  // namespace
 
 hipError_t launch_multidot(int p, double* dots, const void* V, int64_t vstride, int J, const void* w, int64_t n,
-                           int64_t stride, int nrhs, double* partial, hipStream_t s) {
+                           int64_t stride, int nrhs, double* partial, hipStream_t s, int with_self) {
   const int nchunk = (int)((n + kChunk - 1) / kChunk);
   by_prec(p, [&](auto tag) {
     using S = decltype(tag);
     using P = typename PT<S>::stor;
     hipLaunchKernelGGL(k_dot_stage1<S>, dim3(nchunk, nrhs), dim3(kDotWG), 0, s, partial, (const P*)V, vstride, J,
-                       (const P*)w, n, stride, nchunk);
+                       (const P*)w, n, stride, nchunk, with_self);
   });
-  hipLaunchKernelGGL(k_dot_stage2, dim3(J, nrhs), dim3(256), 0, s, dots, partial, J, nchunk);
+  hipLaunchKernelGGL(k_dot_stage2, dim3(J + with_self, nrhs), dim3(256), 0, s, dots, partial, J + with_self, nchunk);
   return hipGetLastError();
 }
 
-// scratch needed by launch_multidot: doubles
+// w_k += sum_j coef V_j,k; norms[2k] = ||w_k||^2 afterwards (fixed summation order)
+hipError_t launch_axpy_norm(int p, void* w, const void* V, int64_t vstride, int J, const double* coef, int64_t n,
+                            int64_t stride, int nrhs, double* norms, double* partial, hipStream_t s) {
+  const int nchunk = (int)((n + kChunk - 1) / kChunk);
+  by_prec(p, [&](auto tag) {
+    using S = decltype(tag);
+    using P = typename PT<S>::stor;
+    hipLaunchKernelGGL(k_axpy_norm<S>, dim3(nchunk, nrhs), dim3(kDotWG), 0, s, (P*)w, (const P*)V, vstride, J, coef,
+                       n, stride, nchunk, partial);
+  });
+  hipLaunchKernelGGL(k_dot_stage2, dim3(1, nrhs), dim3(256), 0, s, norms, partial, 1, nchunk);
+  return hipGetLastError();
+}
+
+// scratch needed by launch_multidot / launch_axpy_norm: doubles
 size_t multidot_partial_doubles(int64_t n, int J, int nrhs) {
-  return (size_t)((n + kChunk - 1) / kChunk) * J * nrhs * 2;
+  return (size_t)((n + kChunk - 1) / kChunk) * (J + 1) * nrhs * 2;
 }
 
 hipError_t launch_multiaxpy(int p, void* w, const void* V, int64_t vstride, int J, const double* coef, int64_t n,

@@ -158,18 +158,22 @@ __device__ __forceinline__ void hop44(Spinor<C> (&acc)[R], const P* const (&in)[
   }
 }
 
-template <typename S, bool CLOVER, int MODE, int R, int W>
+template <typename S, bool CLOVER, int MODE, int R, int W, bool LOOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1))) void k_dslash44(DsArgs<S> a) {
   using C = typename PT<S>::real;
   using P = typename PT<S>::stor;
   const int w = blockIdx.x, nw = gridDim.x;
   const int L = (a.remap && (nw & 7) == 0) ? (w & 7) * (nw >> 3) + (w >> 3) : w;
   const int ng = (a.nrhs + R - 1) / R;
-  const int k0 = (L % ng) * R;
   // blocks are visited in lexicographic order so that neighbouring blocks run
-  // close together in time (and, with the XCD remap, on the same XCD)
-  const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(a.g.lexord[L / ng]);
+  // close together in time (and, with the XCD remap, on the same XCD).  With
+  // LOOP one work-group walks all rhs groups of its block, so the block's
+  // links are fetched from HBM once and re-read from cache.
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(a.g.lexord[LOOP ? L : L / ng]);
   const uint32_t l = threadIdx.x;
+#pragma unroll 1
+  for (int kg = LOOP ? 0 : L % ng; kg < (LOOP ? ng : L % ng + 1); ++kg) {
+  const int k0 = kg * R;
   const int nr = a.nrhs - k0 < R ? a.nrhs - k0 : R;
   const P* in[R];
 #pragma unroll
@@ -219,12 +223,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W > 0 ? W :
         sto(out, ((b * 12u + (uint32_t)(3 * s + c)) << 8) + l, vc(v, (P*)nullptr));
       }
   }
+  }
 }
 
-template <typename S, bool CLOVER, int MODE, int R, int W>
+template <typename S, bool CLOVER, int MODE, int R, int W, bool LOOP = false>
 void launch44(const DsArgs<S>& a, int nb, hipStream_t s) {
-  const unsigned ng = (unsigned)((a.nrhs + R - 1) / R);
-  hipLaunchKernelGGL((k_dslash44<S, CLOVER, MODE, R, W>), dim3((unsigned)nb * ng), dim3(256), 0, s, a);
+  const unsigned ng = LOOP ? 1u : (unsigned)((a.nrhs + R - 1) / R);
+  hipLaunchKernelGGL((k_dslash44<S, CLOVER, MODE, R, W, LOOP>), dim3((unsigned)nb * ng), dim3(256), 0, s, a);
 }
 
 template <typename S, bool CLOVER, int MODE>
@@ -252,7 +257,10 @@ void launch_t(const qmg_ctx* c, void* out, const void* in, const double* tau, in
       case 4: launch44<S, CLOVER, MODE, 1, 4>(a, c->g.nb, s); break;
       case 5: launch44<S, CLOVER, MODE, 2, 0>(a, c->g.nb, s); break;
       case 6: launch44<S, CLOVER, MODE, 2, 2>(a, c->g.nb, s); break;
-      default: launch44<S, CLOVER, MODE, 4, 0>(a, c->g.nb, s); break;
+      case 7: launch44<S, CLOVER, MODE, 4, 0>(a, c->g.nb, s); break;
+      case 8: launch44<S, CLOVER, MODE, 1, 2, true>(a, c->g.nb, s); break;
+      case 9: launch44<S, CLOVER, MODE, 2, 0, true>(a, c->g.nb, s); break;
+      default: launch44<S, CLOVER, MODE, 2, 2, true>(a, c->g.nb, s); break;
     }
     return;
   }

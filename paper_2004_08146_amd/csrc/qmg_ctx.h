@@ -19,13 +19,16 @@ inline int coarse_prec(int p) { return p == QMG_F64 ? QMG_F64 : QMG_F32; }
 // waves-per-SIMD occupancy target W (0: compiler's choice).  Variant 0 is the
 // generic kernel (any block shape).
 struct DsVariant { int R, W; };
-constexpr DsVariant kDsVariants[] = {{0, 0}, {1, 0}, {1, 2}, {1, 3}, {1, 4}, {2, 0}, {2, 2}, {4, 0}};
-constexpr int kNumDsVariants = 8;
+// variants 8..10 walk all rhs groups of a block inside one work-group
+constexpr DsVariant kDsVariants[] = {{0, 0}, {1, 0}, {1, 2}, {1, 3}, {1, 4}, {2, 0}, {2, 2}, {4, 0},
+                                     {1, 2}, {2, 0}, {2, 2}};
+constexpr int kNumDsVariants = 11;
 
 struct Tune {
   int dslash[3][2] = {{1, 1}, {1, 1}, {1, 1}};  // [prec][nrhs == 1 ? 0 : 1] -> variant index
   int dslash_xcd_remap = 1;                      // XCD-aware mapping of work-groups to blocks
   int force_variant = -1;                        // >= 0: use this stencil variant (tuning, tests)
+  int sap_variant = 1;                           // 0 generic SAP; 1 LDS-staged 4^4 SAP (FP32 / BF16)
   int coarse_rhs_tile = 4;                       // right-hand sides per coarse-apply work-group
   bool tuned = false;
 };
@@ -94,7 +97,10 @@ hipError_t launch_coarse_apply(const qmg_ctx* c, int p, void* out, const void* i
 // ---- blas.hip (vectors of n complex per right-hand side, k-th rhs at offset k*stride)
 // dots[k*J + j] = <V_j,k , w_k> for j < J (V_j at base + j*vstride), FP64 results on device
 hipError_t launch_multidot(int p, double* dots, const void* V, int64_t vstride, int J, const void* w,
-                           int64_t n, int64_t stride, int nrhs, double* partial, hipStream_t s);
+                           int64_t n, int64_t stride, int nrhs, double* partial, hipStream_t s, int with_self = 0);
+// w_k += sum_j coef[k*J + j] V_j,k and norms[2k] = ||w_k||^2 of the result
+hipError_t launch_axpy_norm(int p, void* w, const void* V, int64_t vstride, int J, const double* coef, int64_t n,
+                            int64_t stride, int nrhs, double* norms, double* partial, hipStream_t s);
 // w_k += sum_j coef[k*J + j] * V_j,k   (coef complex double on device)
 hipError_t launch_multiaxpy(int p, void* w, const void* V, int64_t vstride, int J, const double* coef,
                             int64_t n, int64_t stride, int nrhs, hipStream_t s);

@@ -224,6 +224,251 @@ __global__ __launch_bounds__(256) void k_sap(SapArgs<S> a) {
   store_spinor(x, g, b, l, xs);
 }
 
+// ---- 4^4 blocks, FP32 arithmetic (FP32 or BF16 storage): one work-group per
+// block walks all right-hand sides.  The block's forward links are staged in
+// LDS once (the block operator only needs links inside the block) and the
+// clover blocks stay in registers, so the minimal-residual iterations touch
+// no global memory; only the residual's faces and the update go to HBM.
+constexpr int kSh44[4] = {6, 4, 2, 0};
+
+template <int MU>
+__device__ __forceinline__ void nb44(uint32_t b, uint32_t l, bool fwd, const int* nbr, uint32_t& bn, uint32_t& ln,
+                                     bool& inside) {
+  constexpr int SH = kSh44[MU];
+  const uint32_t lc = (l >> SH) & 3u;
+  if (fwd) {
+    inside = lc < 3u;
+    bn = inside ? b : (uint32_t)nbr[b * 8 + 2 * MU];
+    ln = inside ? l + (1u << SH) : l - (3u << SH);
+  } else {
+    inside = lc > 0u;
+    bn = inside ? b : (uint32_t)nbr[b * 8 + 2 * MU + 1];
+    ln = inside ? l - (1u << SH) : l + (3u << SH);
+  }
+}
+
+__device__ __forceinline__ Link<float> lds_link(const cpx<float>* Ul, int mu, uint32_t l) {
+  Link<float> u;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u.u[a][c] = Ul[(mu * 9 + 3 * a + c) * 256 + l];
+  return u;
+}
+
+template <typename P>
+__device__ __forceinline__ Spinor<float> gl_spinor(const P* f, uint32_t b, uint32_t l) {
+  Spinor<float> p;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      auto v = cv(ldo(f, ((b * 12u + (uint32_t)(3 * s + c)) << 8) + l));
+      p.s[s][c] = cpx<float>{float(v.re), float(v.im)};
+    }
+  return p;
+}
+
+// residual hop: neighbour spinor from global x, link from LDS when inside the block
+template <int HOP, typename P>
+__device__ __forceinline__ void res_hop44(Spinor<float>& acc, const P* x, const P* U, const cpx<float>* Ul,
+                                          const int* nbr, uint32_t b, uint32_t l) {
+  constexpr int MU = HOP / 2;
+  constexpr bool FWD = HOP % 2 == 0;
+  uint32_t bn, ln;
+  bool inside;
+  nb44<MU>(b, l, FWD, nbr, bn, ln, inside);
+  const Half<float> h = project(gl_spinor(x, bn, ln), MU, FWD);
+  if (FWD) {
+    accum_recon(acc, umul(lds_link(Ul, MU, l), h), MU, true);
+  } else {
+    Link<float> u;
+    if (inside) u = lds_link(Ul, MU, ln);
+    else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          auto v = cv(ldo(U, ((bn * 36u + (uint32_t)(MU * 9 + 3 * a + c)) << 8) + ln));
+          u.u[a][c] = cpx<float>{float(v.re), float(v.im)};
+        }
+    }
+    accum_recon(acc, udagmul(u, h), MU, false);
+  }
+}
+
+// block-restricted hop: neighbour from LDS rho, link from LDS, dropped outside
+template <int HOP>
+__device__ __forceinline__ void blk_hop44(Spinor<float>& acc, const cpx<float>* rh, const cpx<float>* Ul, uint32_t l) {
+  constexpr int MU = HOP / 2;
+  constexpr bool FWD = HOP % 2 == 0;
+  constexpr int SH = kSh44[MU];
+  const uint32_t lc = (l >> SH) & 3u;
+  if (FWD ? lc < 3u : lc > 0u) {
+    const uint32_t ln = FWD ? l + (1u << SH) : l - (1u << SH);
+    const Half<float> h = project(lds_spinor(rh, (int)ln, 256), MU, FWD);
+    const Link<float> u = lds_link(Ul, MU, FWD ? l : ln);
+    accum_recon(acc, FWD ? umul(u, h) : udagmul(u, h), MU, FWD);
+  }
+}
+
+// (m0+4 + C) v - tau Gamma5 v with the clover blocks held in registers
+template <bool CLOVER>
+__device__ __forceinline__ Spinor<float> diag_reg(const cpx<float> (&dg)[2][18], float mass4, const Spinor<float>& v,
+                                                  float tau) {
+  Spinor<float> o;
+  if (CLOVER) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      cpx<float> in[6], w[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) in[i] = v.s[2 * h + i / 3][i % 3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        w[2 * k] = dg[h][k].re * in[2 * k];
+        w[2 * k + 1] = dg[h][k].im * in[2 * k + 1];
+      }
+      int k = 3;
+#pragma unroll
+      for (int i = 1; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+          w[i] = w[i] + dg[h][k] * in[j];
+          w[j] = w[j] + cmul_conj(dg[h][k], in[i]);
+          ++k;
+        }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) o.s[2 * h + i / 3][i % 3] = w[i];
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o.s[s][c] = mass4 * v.s[s][c];
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o.s[s][c] = (s < 2) ? o.s[s][c] - tau * v.s[s][c] : o.s[s][c] + tau * v.s[s][c];
+  return o;
+}
+
+template <typename S, bool CLOVER>
+__global__ __launch_bounds__(256) void k_sap44(SapArgs<S> a) {
+  using P = typename PT<S>::stor;
+  __shared__ cpx<float> Ul[36 * 256];
+  __shared__ cpx<float> rh[12 * 256];
+  __shared__ float red[16];
+  const int w = blockIdx.x, nw = gridDim.x;
+  const int L = ((nw & 7) == 0) ? (w & 7) * (nw >> 3) + (w >> 3) : w;
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(a.first_block + L);
+  const uint32_t l = threadIdx.x;
+  const int* nbr = a.g.nbr;
+#pragma unroll 4
+  for (int i = 0; i < 36; ++i) {
+    auto v = cv(ldo(a.U, ((b * 36u + (uint32_t)i) << 8) + l));
+    Ul[i * 256 + l] = cpx<float>{float(v.re), float(v.im)};
+  }
+  cpx<float> dg[2][18];
+  if (CLOVER) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < 18; ++k) {
+        auto v = cv(ldo(a.diag, ((b * 36u + (uint32_t)(h * 18 + k)) << 8) + l));
+        dg[h][k] = cpx<float>{float(v.re), float(v.im)};
+      }
+  }
+  const float mass4 = float(a.mass4);
+  __syncthreads();
+#pragma unroll 1
+  for (int k = 0; k < a.nrhs; ++k) {
+    P* x = a.x + (size_t)k * a.fstride;
+    const P* f = a.f + (size_t)k * a.fstride;
+    const float tau = float(a.tau[k]);
+    Spinor<float> acc;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc.s[s][c] = czero<float>();
+#pragma unroll 1
+    for (int hop = 0; hop < 8; ++hop) {
+      switch (hop) {
+        case 0: res_hop44<0>(acc, x, a.U, Ul, nbr, b, l); break;
+        case 1: res_hop44<1>(acc, x, a.U, Ul, nbr, b, l); break;
+        case 2: res_hop44<2>(acc, x, a.U, Ul, nbr, b, l); break;
+        case 3: res_hop44<3>(acc, x, a.U, Ul, nbr, b, l); break;
+        case 4: res_hop44<4>(acc, x, a.U, Ul, nbr, b, l); break;
+        case 5: res_hop44<5>(acc, x, a.U, Ul, nbr, b, l); break;
+        case 6: res_hop44<6>(acc, x, a.U, Ul, nbr, b, l); break;
+        default: res_hop44<7>(acc, x, a.U, Ul, nbr, b, l); break;
+      }
+    }
+    Spinor<float> xs = gl_spinor(x, b, l);
+    Spinor<float> rho;
+    {
+      const Spinor<float> d = diag_reg<CLOVER>(dg, mass4, xs, tau);
+      const Spinor<float> fs = gl_spinor(f, b, l);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rho.s[s][c] = fs.s[s][c] - (d.s[s][c] - 0.5f * acc.s[s][c]);
+    }
+#pragma unroll 1
+    for (int it = 0; it < a.n_mr; ++it) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rh[(3 * s + c) * 256 + l] = rho.s[s][c];
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc.s[s][c] = czero<float>();
+#pragma unroll 1
+      for (int hop = 0; hop < 8; ++hop) {
+        switch (hop) {
+          case 0: blk_hop44<0>(acc, rh, Ul, l); break;
+          case 1: blk_hop44<1>(acc, rh, Ul, l); break;
+          case 2: blk_hop44<2>(acc, rh, Ul, l); break;
+          case 3: blk_hop44<3>(acc, rh, Ul, l); break;
+          case 4: blk_hop44<4>(acc, rh, Ul, l); break;
+          case 5: blk_hop44<5>(acc, rh, Ul, l); break;
+          case 6: blk_hop44<6>(acc, rh, Ul, l); break;
+          default: blk_hop44<7>(acc, rh, Ul, l); break;
+        }
+      }
+      Spinor<float> q = diag_reg<CLOVER>(dg, mass4, rho, tau);
+      float v[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          q.s[s][c] = q.s[s][c] - 0.5f * acc.s[s][c];
+          const cpx<float> t = cmul_conj(q.s[s][c], rho.s[s][c]);
+          v[0] += t.re;
+          v[1] += t.im;
+          v[2] += norm2(q.s[s][c]);
+        }
+      block_sum<float, 3>(v, red);
+      cpx<float> alpha = czero<float>();
+      if (v[2] > 0.f) alpha = cpx<float>{v[0] / v[2], v[1] / v[2]};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          xs.s[s][c] = xs.s[s][c] + alpha * rho.s[s][c];
+          rho.s[s][c] = rho.s[s][c] - alpha * q.s[s][c];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        sto(x, ((b * 12u + (uint32_t)(3 * s + c)) << 8) + l, vc(xs.s[s][c], (P*)nullptr));
+  }
+}
+
 template <typename S>
 void launch_s(const qmg_ctx* c, int p, void* x, const void* f, const double* tau, int nrhs, int colour,
               int n_mr, hipStream_t s) {
@@ -244,6 +489,15 @@ void launch_s(const qmg_ctx* c, int p, void* x, const void* f, const double* tau
   for (int i = 0; i < QMG_MAXRHS; ++i) a.tau[i] = i < nrhs ? tau[i] : 0.0;
   const int bs = 1 << c->g.bs_log;
   size_t lds = sizeof(cpx<R>) * 12 * bs + sizeof(R) * 3 * std::max(bs, 8);
+  const bool b44 = c->g.block[0] == 4 && c->g.block[1] == 4 && c->g.block[2] == 4 && c->g.block[3] == 4;
+  if constexpr (!std::is_same<S, double>::value) {
+    if (b44 && c->tune.sap_variant == 1) {
+      dim3 grid((unsigned)a.nblk);
+      if (c->clover) hipLaunchKernelGGL((k_sap44<S, true>), grid, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((k_sap44<S, false>), grid, dim3(256), 0, s, a);
+      return;
+    }
+  }
   dim3 grid((unsigned)(a.nblk * nrhs));
   if (c->clover) hipLaunchKernelGGL((k_sap<S, true>), grid, dim3(bs), lds, s, a);
   else hipLaunchKernelGGL((k_sap<S, false>), grid, dim3(bs), lds, s, a);

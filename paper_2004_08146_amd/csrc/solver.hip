@@ -139,30 +139,51 @@ struct Space {
     if (e != hipSuccess) return hip_err(c, e, "scale");
     return QMG_OK;
   }
-  // one CGS2 Arnoldi step on basis V_0..V_j with new vector w; h[k] gets j+2 entries
+  // One Arnoldi step on basis V_0..V_j with new vector w; h[k] gets j+2 entries.
+  // Classical Gram-Schmidt with the DGKS criterion: a second pass is made when
+  // the projection removed more than half of the squared norm of some column
+  // (||w_new|| < ||w|| / sqrt(2)); the new norm comes out of the update pass.
   qmg_status arnoldi(std::vector<std::vector<cd>>& h, void* V, int j, void* w) {
     const int J = j + 1;
     h.assign(nrhs, std::vector<cd>(j + 2, cd(0)));
+    double* d = (double*)ws_get(c, "sp_dots", sizeof(double) * 2 * (J + 1) * nrhs);
+    double* part = (double*)ws_get(c, "sp_part", sizeof(double) * multidot_partial_doubles(n, J + 1, nrhs));
+    double* dc = (double*)ws_get(c, "sp_coef", sizeof(double) * 2 * J * nrhs);
+    if (!d || !part || !dc) return set_err(c, QMG_E_NOMEM, "out of device memory (Arnoldi)");
+    double* hd = host_buf(c, "dots", 2 * (J + 1) * nrhs);
+    double* hc = host_buf(c, "coef", 2 * J * nrhs);
+    std::vector<double> before(nrhs), after(nrhs);
     for (int pass = 0; pass < 2; ++pass) {
-      std::vector<cd> d;
-      qmg_status st = dots(d, V, J, vstride(), w);
-      if (st != QMG_OK) return st;
-      std::vector<cd> coef(d.size());
-      for (int k = 0; k < nrhs; ++k)
+      const int self = pass == 0 ? 1 : 0;
+      hipError_t e = launch_multidot(p, d, V, vstride(), J, w, n, n, nrhs, part, s, self);
+      if (e == hipSuccess) e = hipMemcpyAsync(hd, d, sizeof(double) * 2 * (J + self) * nrhs, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_err(c, e, "Arnoldi dots");
+      for (int k = 0; k < nrhs; ++k) {
         for (int i = 0; i < J; ++i) {
-          h[k][i] += d[(size_t)k * J + i];
-          coef[(size_t)k * J + i] = -d[(size_t)k * J + i];
+          const double* q = hd + 2 * ((size_t)k * (J + self) + i);
+          h[k][i] += cd(q[0], q[1]);
+          hc[2 * ((size_t)k * J + i)] = -q[0];
+          hc[2 * ((size_t)k * J + i) + 1] = -q[1];
         }
-      st = axpy(w, V, J, vstride(), coef);
-      if (st != QMG_OK) return st;
+        if (self) before[k] = hd[2 * ((size_t)k * (J + 1) + J)];
+      }
+      e = hipMemcpyAsync(dc, hc, sizeof(double) * 2 * J * nrhs, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = launch_axpy_norm(p, w, V, vstride(), J, dc, n, n, nrhs, d, part, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(hd, d, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_err(c, e, "Arnoldi update");
+      bool again = false;
+      for (int k = 0; k < nrhs; ++k) {
+        after[k] = hd[2 * k];
+        if (!std::isfinite(after[k]) || !std::isfinite(before[k]))
+          return set_err(c, QMG_E_NUMERIC, "non-finite norm in Arnoldi step");
+        if (after[k] < 0.5 * before[k]) again = true;
+        before[k] = after[k];
+      }
+      if (!again) break;
     }
-    std::vector<double> nn;
-    qmg_status st = norms(nn, w);
-    if (st != QMG_OK) return st;
-    for (int k = 0; k < nrhs; ++k) {
-      if (!std::isfinite(nn[k])) return set_err(c, QMG_E_NUMERIC, "non-finite norm in Arnoldi step");
-      h[k][j + 1] = nn[k];
-    }
+    for (int k = 0; k < nrhs; ++k) h[k][j + 1] = std::sqrt(std::max(0.0, after[k]));
     return QMG_OK;
   }
 };

@@ -54,6 +54,11 @@ bool load_cache(qmg_ctx* c, const std::string& path, const std::string& key) {
         ++found;
       }
     }
+  const std::string ks = "\"" + key + "|sap\":";
+  const size_t pos = txt.find(ks);
+  int v = -1;
+  if (pos != std::string::npos && std::sscanf(txt.c_str() + pos + ks.size(), " %d", &v) == 1 && (v == 0 || v == 1))
+    c->tune.sap_variant = v;
   return found == 6;
 }
 
@@ -109,6 +114,37 @@ qmg_status tune_run(qmg_ctx* c, const char* path) {
          << ",\n  \"" << key << "|dslash|" << kPrecName[p] << "|" << cls << "|ms\": [" << times.str() << "]";
       first = false;
     }
+  // SAP kernel choice (FP32 arithmetic paths), one colour half-sweep on 16 rhs
+  const int sap_default = c->tune.sap_variant;
+  for (int p = 1; p < 3 && st == QMG_OK && c->sap_ok && b44; ++p) {
+    const int n = 16;
+    const size_t bytes = field_elems(c) * cbytes(p) * n;
+    void* x = ws_get(c, "tune_in", bytes);
+    void* f = ws_get(c, "tune_out", bytes);
+    if (!x || !f) { st = set_err(c, QMG_E_NOMEM, "autotune: out of device memory"); break; }
+    hipError_t e = launch_fill_zero(x, bytes, s);
+    if (e == hipSuccess) e = launch_fill_zero(f, bytes, s);
+    double best_ms = 1e30;
+    int best = sap_default;
+    std::ostringstream times;
+    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+      c->tune.sap_variant = v;
+      e = launch_sap_colour(c, p, x, f, tau.data(), n, 0, 3, s);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_sap_colour(c, p, x, f, tau.data(), n, 0, 3, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      ms /= 3;
+      times << (v ? ", " : "") << ms;
+      if (ms < best_ms) { best_ms = ms; best = v; }
+    }
+    if (e != hipSuccess) { st = hip_err(c, e, "autotune sap"); break; }
+    c->tune.sap_variant = best;
+    js << ",\n  \"" << key << "|sap|" << kPrecName[p] << "|ms\": [" << times.str() << "]";
+  }
+  if (st == QMG_OK) js << ",\n  \"" << key << "|sap\": " << c->tune.sap_variant;
   js << "\n}\n";
   c->tune.force_variant = -1;
   hipEventDestroy(e0);

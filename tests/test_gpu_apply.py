@@ -130,7 +130,7 @@ def _force_variant(lat, tmp_path, dims, block, clover, v):
     lat.autotune(str(path))
 
 
-@pytest.mark.parametrize("variant", range(8))
+@pytest.mark.parametrize("variant", range(11))
 def test_stencil_variants(variant, tmp_path):
     """Every launch variant of the stencil (generic, 4^4 kernels with 1/2/4 rhs per
     thread and occupancy targets) against the oracle, with a ragged rhs batch."""

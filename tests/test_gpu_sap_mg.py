@@ -37,18 +37,33 @@ def test_sap_parity(dims, block):
         assert rel_err(got[k], ref) < 1e-12
 
 
+def _force_sap(lat, tmp_path, dims, block, clover, v):
+    key = "gfx950|%s|%s|clover=%d" % ("x".join(map(str, dims)), "x".join(map(str, block)), clover)
+    entries = ['"%s|dslash|%s|%d": 1' % (key, p, c) for p in ("f64", "f32", "bf16") for c in (0, 1)]
+    entries.append('"%s|sap": %d' % (key, v))
+    path = tmp_path / ("tune_sap_%d.json" % v)
+    path.write_text("{\n" + ",\n".join(entries) + "\n}\n")
+    lat.autotune(str(path))
+
+
+@pytest.mark.parametrize("sapv", [0, 1])
 @pytest.mark.parametrize("prec,tol", [("f32", 2e-5), ("bf16", 5e-2)])
-def test_sap_reduced_precision(prec, tol):
-    case("sap 8^4 " + prec)
+def test_sap_reduced_precision(prec, tol, sapv, tmp_path):
+    """FP32 / BF16-storage SAP (both kernels: generic and LDS-staged 4^4) on 2 rhs."""
+    case("sap 8^4 %s variant %d" % (prec, sapv))
     dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
     qmg, lat, op = _op(dims, block)
-    f = random_spinors(dims, 1, seed_for(2, "b"))
-    xg = lat.field(1, prec)
+    _force_sap(lat, tmp_path, dims, block, 1, sapv)
+    f = random_spinors(dims, 2, seed_for(2, "b"))
+    taus = [0.01, -0.15]
+    xg = lat.field(2, prec)
     fg = lat.pack(dev(f), prec)
-    lat.sap_smooth(xg, fg, [0.01], 1, nsweep=3, n_mr=3, prec=prec)
-    got = host(lat.unpack(xg, 1, prec))[0]
-    ref = sap.sap(op, host(lat.unpack(fg, 1, prec))[0], np.zeros_like(f[0]), 0.01, block, 3, 3)
-    assert rel_err(got, ref) < tol
+    lat.sap_smooth(xg, fg, taus, 2, nsweep=3, n_mr=3, prec=prec)
+    got = host(lat.unpack(xg, 2, prec))
+    fin = host(lat.unpack(fg, 2, prec))
+    for k in range(2):
+        ref = sap.sap(op, fin[k], np.zeros_like(f[0]), taus[k], block, 3, 3)
+        assert rel_err(got[k], ref) < tol
 
 
 def _mg(dims, block, ntv=8, csw=1.0):
