@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the extra FP64/BF16 solves")
     ap.add_argument("--tune-cache", type=str, default=None, help="autotuner JSON cache (default: fresh)")
+    ap.add_argument("--graph", type=int, default=1, help="1: V-cycle replayed as a HIP graph (fixed coarse steps)")
+    ap.add_argument("--coarse-iters", type=int, default=4, help="coarse GMRES steps in graph mode")
     ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",
                     help="kernels: only a few launches of the hot kernels and a 1 GiB copy (for counter runs)")
     args = ap.parse_args()
@@ -181,11 +183,6 @@ def main():
 
     lat = qmg.Lattice(dims, (4, 4, 4, 4))
     lat.set_gauge(torch.from_numpy(U).cuda(), m0, csw)
-    tune_path = args.tune_cache or os.path.join("/tmp", "qmg_tune_%d.json" % os.getpid())
-    t0 = time.time()
-    lat.autotune(tune_path)
-    tuning = json.load(open(tune_path))
-    print("[bench] autotune %.1f s: %s" % (time.time() - t0, json.dumps(tuning)), file=sys.stderr, flush=True)
     bg = lat.pack(torch.from_numpy(b).cuda())
     ntv = 24
     W0 = lat.pack(device_gaussian_spinors(dims, ntv, seed_for(5, "W")))
@@ -196,10 +193,16 @@ def main():
     setup_s = time.time() - t0
     del W0
     print("[bench] setup %.2f s" % setup_s, file=sys.stderr, flush=True)
+    tune_path = args.tune_cache or os.path.join("/tmp", "qmg_tune_%d.json" % os.getpid())
+    t0 = time.time()
+    lat.autotune(tune_path)
+    tuning = json.load(open(tune_path))
+    print("[bench] autotune %.1f s: %s" % (time.time() - t0, json.dumps(tuning)), file=sys.stderr, flush=True)
 
-    def solve(prec):
+    def solve(prec, graph=args.graph):
         x = lat.field(nrhs)
-        prm = qmg.default_params(mg_prec=prec, restart=args.restart, maxiter=2000)
+        prm = qmg.default_params(mg_prec=prec, restart=args.restart, maxiter=2000, use_graph=graph,
+                                 coarse_maxiter=args.coarse_iters if graph else 50)
         st, stats = lat.solve_shifted(x, bg, taus, nrhs, prm)
         return st, stats
 
@@ -224,6 +227,13 @@ def main():
 
     extra = {}
     if not args.quick:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, stats = solve("f32", graph=1 - args.graph)
+        torch.cuda.synchronize()
+        extra["f32_graph%d" % (1 - args.graph)] = {
+            "ms": 1000.0 * (time.perf_counter() - t1), "status": st,
+            "max_true_relres": max(s["true_relres"] for s in stats), "iters": [s["iters"] for s in stats]}
         for prec in ("f64", "bf16"):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -273,6 +283,7 @@ def main():
                    "block": [4, 4, 4, 4], "ntv": ntv, "restart": args.restart, "setup_iters": args.setup_iters},
         "converged": ok, "max_true_relres": relres, "fgmres_iters": iters, "setup_s": setup_s,
         "solve_ms": {"mixed_f32": ms_step, **{"%s_precond" % k: v["ms"] for k, v in extra.items()}},
+        "graph": args.graph, "coarse_iters_graph": args.coarse_iters,
         "solve_detail": extra,
         "q_apply": qapply,
         "sap_sweep_f32": {"ms": sap_ms, "gbps": sap_bytes / sap_ms / 1e6, "hbm_frac": sap_bytes / sap_ms / 1e6 / HBM_PEAK_GBS},

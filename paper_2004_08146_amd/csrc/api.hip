@@ -28,6 +28,7 @@ void* ws_get(qmg_ctx* c, const std::string& name, size_t bytes) {
     hipDeviceSynchronize();
     hipFree(it->second.first);
     c->ws.erase(it);
+    drop_graphs(c);  // captured graphs may hold the old address
   }
   void* p = nullptr;
   if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
@@ -41,6 +42,13 @@ void ws_release(qmg_ctx* c, const std::string& name) {
   hipDeviceSynchronize();
   hipFree(it->second.first);
   c->ws.erase(it);
+  drop_graphs(c);
+}
+
+void drop_graphs(qmg_ctx* c) {
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  c->ws_epoch++;
 }
 
 namespace {
@@ -199,7 +207,8 @@ qmg_status qmg_destroy(qmg_ctx* c) {
   if (!c) return QMG_OK;
   hipSetDevice(c->device);
   hipDeviceSynchronize();
-  if (c->graph) hipGraphExecDestroy(c->graph);
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   for (int p = 0; p < 3; ++p) {
     free_ptr(c->U[p]);
     free_ptr(c->Dg[p]);
@@ -283,6 +292,7 @@ qmg_status qmg_set_gauge(qmg_ctx* c, const double* U, double m0, double csw, hip
   c->csw = csw;
   c->have_gauge = true;
   c->have_mg = false;
+  drop_graphs(c);  // graphs carry m0 and the clover flag as kernel arguments
   return QMG_OK;
 }
 

@@ -89,6 +89,103 @@ __global__ __launch_bounds__(64) void k_coarse_apply(Geom g, typename PT<C>::sto
   }
 }
 
+// ---- MFMA coarse apply (many right-hand sides): per coarse site b and tile of
+// 16 rhs, Out (2ntv x 16) = sum_d D_c[b][d] (2ntv x 2ntv) In_{nbr(b,d)} (2ntv x 16),
+// a complex GEMM done as four real 16x16x4 MFMA products per k-step
+// (C_re += A_re B_re - A_im B_im, C_im += A_re B_im + A_im B_re).  One wave
+// per work-group; the 16 rhs of a neighbour block are staged in LDS.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+typedef double md4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mf4 mfma(float a, float b, mf4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ md4 mfma(double a, double b, md4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+template <typename R> struct MAcc;
+template <> struct MAcc<float> { using T = mf4; };
+template <> struct MAcc<double> { using T = md4; };
+
+// row of output register r of lane l inside a 16x16 tile
+template <typename R> __device__ __forceinline__ int mrow(int l, int r);
+template <> __device__ __forceinline__ int mrow<float>(int l, int r) { return 4 * (l >> 4) + r; }
+template <> __device__ __forceinline__ int mrow<double>(int l, int r) { return 4 * r + (l >> 4); }
+
+template <typename S, typename C, int NT>
+__global__ __launch_bounds__(64) void k_coarse_mfma(Geom g, typename PT<C>::stor* out, const typename PT<S>::stor* DcT,
+                                                    const typename PT<C>::stor* in, int nrhs, TauArr tau) {
+  using R = typename PT<C>::real;
+  using AT = typename MAcc<R>::T;
+  constexpr int NC = 16 * NT;  // 2 ntv
+  __shared__ cpx<R> Bs[NC][16];
+  __shared__ cpx<R> Bself[NC][16];
+  const int b = blockIdx.x, n0 = blockIdx.y * 16, l = threadIdx.x;
+  const int ln = l & 15, lk = l >> 4;
+  AT acc_re[NT], acc_im[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc_re[t] = AT{0, 0, 0, 0};
+    acc_im[t] = AT{0, 0, 0, 0};
+  }
+  const auto* Db = DcT + (int64_t)b * 9 * NC * NC;
+#pragma unroll 1
+  for (int d = 0; d < 9; ++d) {
+    const int nbk = d == 0 ? b : g.nbr[b * 8 + d - 1];
+    __syncthreads();
+    for (int idx = l; idx < NC * 16; idx += 64) {
+      const int j = idx % NC, n = idx / NC;
+      const cpx<R> v = n0 + n < nrhs ? ldcv<R>(in, ((int64_t)(n0 + n) * g.nb + nbk) * NC + j) : czero<R>();
+      Bs[j][n] = v;
+      if (d == 0) Bself[j][n] = v;
+    }
+    __syncthreads();
+    const auto* Dd = Db + (int64_t)d * NC * NC;
+#pragma unroll 2
+    for (int j0 = 0; j0 < NC; j0 += 4) {
+      const cpx<R> bv = Bs[j0 + lk][ln];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const cpx<R> av = ldcv<R>(Dd, (int64_t)(j0 + lk) * NC + 16 * t + ln);
+        acc_re[t] = mfma(av.re, bv.re, acc_re[t]);
+        acc_re[t] = mfma(-av.im, bv.im, acc_re[t]);
+        acc_im[t] = mfma(av.re, bv.im, acc_im[t]);
+        acc_im[t] = mfma(av.im, bv.re, acc_im[t]);
+      }
+    }
+  }
+  const int n = n0 + ln;
+  if (n >= nrhs) return;
+  const R tn = R(tau.t[n]);
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * t + mrow<R>(l, r);
+      const R g5 = i < NC / 2 ? R(1) : R(-1);
+      const cpx<R> self = Bself[i][ln];
+      const cpx<R> v = {acc_re[t][r] - tn * g5 * self.re, acc_im[t][r] - tn * g5 * self.im};
+      stcv(out, ((int64_t)n * g.nb + b) * NC + i, v);
+    }
+}
+
+template <typename S>
+void capply_mfma(const qmg_ctx* c, int p, void* out, const void* in, const TauArr& tau, int nrhs, hipStream_t s) {
+  using P = typename PT<S>::stor;
+  dim3 grid(c->g.nb, (nrhs + 15) / 16);
+  // 2 ntv = 48 (ntv = 24) -> 3 row tiles; 2 ntv = 32 -> 2; 2 ntv = 16 -> 1
+  const int nt = (2 * c->ntv) / 16;
+  auto go = [&](auto ntc) {
+    constexpr int NT = decltype(ntc)::value;
+    if (p == QMG_F64)
+      hipLaunchKernelGGL((k_coarse_mfma<S, double, NT>), grid, dim3(64), 0, s, c->g, (double2*)out, (const P*)c->Dc[p],
+                         (const double2*)in, nrhs, tau);
+    else
+      hipLaunchKernelGGL((k_coarse_mfma<S, float, NT>), grid, dim3(64), 0, s, c->g, (float2*)out, (const P*)c->Dc[p],
+                         (const float2*)in, nrhs, tau);
+  };
+  if (nt == 3) go(std::integral_constant<int, 3>{});
+  else if (nt == 2) go(std::integral_constant<int, 2>{});
+  else go(std::integral_constant<int, 1>{});
+}
+
 template <typename S, int T>
 void capply_t(const qmg_ctx* c, int p, void* out, const void* in, const double* htau, int nrhs, hipStream_t s) {
   using P = typename PT<S>::stor;
@@ -106,6 +203,18 @@ void capply_t(const qmg_ctx* c, int p, void* out, const void* in, const double* 
 
 template <typename S>
 void capply_s(const qmg_ctx* c, int p, void* out, const void* in, const double* dtau, int nrhs, hipStream_t s) {
+  // MFMA path when the coarse dimension is a multiple of 16 (ntv = 8, 16, 24) and
+  // enough right-hand sides share each matrix block
+  if (c->tune.coarse_mfma && (2 * c->ntv) % 16 == 0 && 2 * c->ntv <= 48 && nrhs >= c->tune.coarse_mfma_min_rhs) {
+    TauArr t;
+    for (int i = 0; i < QMG_MAXRHS; ++i) t.t[i] = i < nrhs ? dtau[i] : 0.0;
+    if constexpr (std::is_same<S, double>::value) {
+      if (p == QMG_F64) { capply_mfma<S>(c, p, out, in, t, nrhs, s); return; }
+    } else {
+      capply_mfma<S>(c, p, out, in, t, nrhs, s);
+      return;
+    }
+  }
   if (nrhs >= 4) capply_t<S, 4>(c, p, out, in, dtau, nrhs, s);
   else if (nrhs == 2) capply_t<S, 2>(c, p, out, in, dtau, nrhs, s);
   else capply_t<S, 1>(c, p, out, in, dtau, nrhs, s);

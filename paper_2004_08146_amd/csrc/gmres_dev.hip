@@ -1,0 +1,162 @@
+// Device-resident GMRES scalars (Hessenberg column, Givens rotations,
+// back-substitution) so a fixed-step coarse GMRES -- and with it the whole
+// V-cycle -- runs without host round trips and can be captured in a HIP graph.
+// One thread per right-hand side; the rotations follow the same convention as
+// the host solver: [[c, s], [-conj(s), c]] [a; b] = [r; 0], c real.
+#include "qmg_ctx.h"
+
+namespace {
+
+struct GmState {
+  double* H;     // [nrhs][m+1][m] complex (row-major: (i, j) at i*m + j)
+  double* g;     // [nrhs][m+1] complex
+  double* cs;    // [nrhs][m]
+  double* sn;    // [nrhs][m] complex
+  double* beta;  // [nrhs]
+  int m;
+};
+
+__device__ inline cpx<double> ldz(const double* p, int64_t i) { return {p[2 * i], p[2 * i + 1]}; }
+__device__ inline void stz(double* p, int64_t i, cpx<double> v) { p[2 * i] = v.re; p[2 * i + 1] = v.im; }
+
+// beta = ||r||, a = 1/beta (0 if beta == 0), g = (beta, 0, ...), H = 0
+__global__ void k_gm_init(GmState st, const double* norms, double* a, int nrhs) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nrhs) return;
+  const double b = sqrt(fmax(norms[2 * k], 0.0));
+  st.beta[k] = b;
+  a[2 * k] = b > 0 ? 1.0 / b : 0.0;
+  a[2 * k + 1] = 0.0;
+  const int m = st.m;
+  for (int i = 0; i <= m; ++i) stz(st.g, (int64_t)k * (m + 1) + i, cpx<double>{i == 0 ? b : 0.0, 0.0});
+  for (int i = 0; i < (m + 1) * m; ++i) stz(st.H, (int64_t)k * (m + 1) * m + i, czero<double>());
+}
+
+// one classical Gram-Schmidt pass: H[:, j] += dots, coef = -dots
+__global__ void k_gm_coef(GmState st, const double* dots, double* coef, int j, int nrhs) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nrhs) return;
+  const int J = j + 1, m = st.m;
+  for (int i = 0; i < J; ++i) {
+    const cpx<double> d = ldz(dots, (int64_t)k * J + i);
+    const int64_t hi = (int64_t)k * (m + 1) * m + (int64_t)i * m + j;
+    stz(st.H, hi, ldz(st.H, hi) + d);
+    stz(coef, (int64_t)k * J + i, -d);
+  }
+}
+
+// close column j: h_{j+1,j} = ||w||, rotate, update g, a = 1/h_{j+1,j}
+__global__ void k_gm_col(GmState st, const double* norms, double* a, int j, int nrhs) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nrhs) return;
+  const int m = st.m;
+  double* H = st.H + (int64_t)k * (m + 1) * m * 2;
+  double* g = st.g + (int64_t)k * (m + 1) * 2;
+  double* cs = st.cs + (int64_t)k * m;
+  double* sn = st.sn + (int64_t)k * m * 2;
+  const double hn = sqrt(fmax(norms[2 * k], 0.0));
+  cpx<double> h[2];
+  for (int i = 0; i < j; ++i) {
+    const cpx<double> hi = ldz(H, (int64_t)i * m + j), hi1 = ldz(H, (int64_t)(i + 1) * m + j);
+    const double c = cs[i];
+    const cpx<double> s = ldz(sn, i);
+    stz(H, (int64_t)i * m + j, c * hi + s * hi1);
+    stz(H, (int64_t)(i + 1) * m + j, c * hi1 - conj(s) * hi);
+  }
+  h[0] = ldz(H, (int64_t)j * m + j);
+  h[1] = cpx<double>{hn, 0.0};
+  double c;
+  cpx<double> s;
+  const double na = sqrt(norm2(h[0])), nb = hn;
+  if (nb == 0.0) { c = 1.0; s = czero<double>(); }
+  else if (na == 0.0) { c = 0.0; s = cpx<double>{1.0, 0.0}; }
+  else {
+    const double rho = sqrt(na * na + nb * nb);
+    c = na / rho;
+    s = (1.0 / (na * rho)) * (h[0] * conj(h[1]));
+  }
+  cs[j] = c;
+  stz(sn, j, s);
+  stz(H, (int64_t)j * m + j, c * h[0] + s * h[1]);
+  const cpx<double> gj = ldz(g, j);
+  stz(g, j + 1, -(conj(s) * gj));
+  stz(g, j, c * gj);
+  a[2 * k] = hn > 0 ? 1.0 / hn : 0.0;
+  a[2 * k + 1] = 0.0;
+}
+
+// y = R^{-1} g (R: the rotated Hessenberg, kk columns) -> coef[k][0..kk)
+__global__ void k_gm_solve(GmState st, double* coef, int kk, int nrhs) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nrhs) return;
+  const int m = st.m;
+  const double* H = st.H + (int64_t)k * (m + 1) * m * 2;
+  const double* g = st.g + (int64_t)k * (m + 1) * 2;
+  for (int i = kk - 1; i >= 0; --i) {
+    cpx<double> t = ldz(g, i);
+    for (int l = i + 1; l < kk; ++l) t = t - ldz(H, (int64_t)i * m + l) * ldz(coef, (int64_t)k * kk + l);
+    const cpx<double> d = ldz(H, (int64_t)i * m + i);
+    const double dd = norm2(d);
+    // a zero pivot only follows an exact breakdown; that column adds nothing
+    stz(coef, (int64_t)k * kk + i, dd > 0 ? cpx<double>{(t.re * d.re + t.im * d.im) / dd, (t.im * d.re - t.re * d.im) / dd}
+                                         : czero<double>());
+  }
+}
+
+}  // namespace
+
+// Fixed-step coarse GMRES with every scalar on the device (graph-capturable).
+// Work buffers come from ws (allocate them before a capture with the same sizes).
+qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
+                               hipStream_t s) {
+  const int cp = coarse_prec(p);
+  const int64_t n = (int64_t)coarse_elems(c);
+  const size_t vb = (size_t)n * cbytes(cp);
+  const size_t bb = vb * nrhs;
+  const int m = iters;
+  void* V = ws_get(c, "cg_V", bb * (m + 1));
+  void* w = ws_get(c, "cg_w", bb);
+  double* dots = (double*)ws_get(c, "gd_dots", sizeof(double) * 2 * (m + 2) * nrhs);
+  double* part = (double*)ws_get(c, "gd_part", sizeof(double) * multidot_partial_doubles(n, m + 2, nrhs));
+  double* coef = (double*)ws_get(c, "gd_coef", sizeof(double) * 2 * (m + 1) * nrhs);
+  double* a = (double*)ws_get(c, "gd_a", sizeof(double) * 2 * nrhs);
+  double* nrm = (double*)ws_get(c, "gd_nrm", sizeof(double) * 2 * nrhs);
+  GmState st;
+  st.m = m;
+  st.H = (double*)ws_get(c, "gd_H", sizeof(double) * 2 * (m + 1) * m * nrhs);
+  st.g = (double*)ws_get(c, "gd_g", sizeof(double) * 2 * (m + 1) * nrhs);
+  st.cs = (double*)ws_get(c, "gd_cs", sizeof(double) * m * nrhs);
+  st.sn = (double*)ws_get(c, "gd_sn", sizeof(double) * 2 * m * nrhs);
+  st.beta = (double*)ws_get(c, "gd_beta", sizeof(double) * nrhs);
+  if (!V || !w || !dots || !part || !coef || !a || !nrm || !st.H || !st.g || !st.cs || !st.sn || !st.beta)
+    return set_err(c, QMG_E_NOMEM, "out of device memory (device GMRES)");
+  const dim3 g1((nrhs + 63) / 64), b1(64);
+  const int64_t vs = n * nrhs;
+  hipError_t e = launch_multidot(cp, nrm, r, 0, 0, r, n, n, nrhs, part, s, 1);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_gm_init, g1, b1, 0, s, st, nrm, a, nrhs);
+    e = launch_scale(cp, V, r, a, n, n, nrhs, s);
+  }
+  for (int j = 0; j < m && e == hipSuccess; ++j) {
+    char* Vj = (char*)V + (size_t)j * bb;
+    e = launch_coarse_apply(c, p, w, Vj, tau, nrhs, s);
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+      e = launch_multidot(cp, dots, V, vs, j + 1, w, n, n, nrhs, part, s, 0);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_gm_coef, g1, b1, 0, s, st, dots, coef, j, nrhs);
+        e = launch_axpy_norm(cp, w, V, vs, j + 1, coef, n, n, nrhs, nrm, part, s);
+      }
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_gm_col, g1, b1, 0, s, st, nrm, a, j, nrhs);
+      if (j + 1 < m) e = launch_scale(cp, (char*)V + (size_t)(j + 1) * bb, w, a, n, n, nrhs, s);
+    }
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_gm_solve, g1, b1, 0, s, st, coef, m, nrhs);
+    e = launch_fill_zero(y, bb, s);
+  }
+  if (e == hipSuccess) e = launch_multiaxpy(cp, y, V, vs, m, coef, n, n, nrhs, s);
+  if (e != hipSuccess) return hip_err(c, e, "device GMRES");
+  return QMG_OK;
+}

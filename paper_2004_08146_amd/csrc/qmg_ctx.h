@@ -30,6 +30,8 @@ struct Tune {
   int force_variant = -1;                        // >= 0: use this stencil variant (tuning, tests)
   int sap_variant = 1;                           // 0 generic SAP; 1 LDS-staged 4^4 SAP (FP32 / BF16)
   int coarse_rhs_tile = 4;                       // right-hand sides per coarse-apply work-group
+  int coarse_mfma = 1;                           // MFMA coarse apply for many right-hand sides
+  int coarse_mfma_min_rhs = 4;                   // smallest batch that takes the MFMA path
   bool tuned = false;
 };
 
@@ -58,8 +60,9 @@ struct qmg_ctx {
   std::map<std::string, std::vector<double>> hbuf;  // host staging for small Krylov data
   std::string err;
   Tune tune;
-  hipGraphExec_t graph = nullptr;
-  std::string graph_key;
+  std::map<std::string, hipGraphExec_t> graphs;  // captured V-cycles by (buffers, shifts, parameters)
+  uint64_t ws_epoch = 0;                          // bumped whenever a workspace buffer moves
+  hipStream_t cap_stream = nullptr;               // library stream used only to record graphs
 };
 
 size_t field_elems(const qmg_ctx* c);   // complex elements in one fine field
@@ -68,6 +71,7 @@ size_t coarse_elems(const qmg_ctx* c);  // complex elements in one coarse vector
 // named, lazily grown device workspace (never shrinks; freed by qmg_destroy)
 void* ws_get(qmg_ctx* c, const std::string& name, size_t bytes);
 void ws_release(qmg_ctx* c, const std::string& name);
+void drop_graphs(qmg_ctx* c);
 
 // ---- layout.hip
 hipError_t launch_pack(const Geom& g, void* out, int p, const double* canon, int nrhs, hipStream_t s);
@@ -120,6 +124,8 @@ hipError_t launch_force(const qmg_ctx* c, double* dU, double* dUb, const void* p
 // ---- solver.hip
 qmg_status solver_coarse_gmres(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs,
                                int iters, double tol, int* iters_done, hipStream_t s);
+qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
+                               hipStream_t s);
 qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs,
                          const qmg_params* prm, int* coarse_iters, hipStream_t s);
 qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, int nrhs,

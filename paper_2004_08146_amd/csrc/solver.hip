@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <limits>
 #include <vector>
@@ -255,8 +256,67 @@ qmg_status solver_coarse_gmres(qmg_ctx* c, int p, void* y, const void* r, const 
 }
 
 // ----------------------------------------------------------------- V-cycle --
+// graph_safe: the coarse GMRES runs a fixed number of steps with its scalars on
+// the device, so the whole V-cycle is a pure kernel sequence (no host sync).
+static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
+                              int* coarse_iters, hipStream_t s, bool graph_safe);
+
 qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
                          int* coarse_iters, hipStream_t s) {
+  if (!prm->use_graph) return vcycle_body(c, z, r, tau, nrhs, prm, coarse_iters, s, false);
+  // HIP-graph mode: capture the V-cycle once per (buffers, shifts, parameters) and replay it
+  std::string key;
+  {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%p|%p|%d|%d|%d|%d|%d|%d|", z, r, nrhs, prm->nu_post, prm->n_mr,
+                  prm->coarse_maxiter, (int)prm->mg_prec, prm->use_coarse);
+    key = buf;
+    for (int k = 0; k < nrhs; ++k) {
+      std::snprintf(buf, sizeof(buf), "%.17g,", tau[k]);
+      key += buf;
+    }
+  }
+  if (coarse_iters && prm->use_coarse && c->have_mg) *coarse_iters += prm->coarse_maxiter;
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) {
+    hipError_t e = hipGraphLaunch(it->second, s);
+    return e == hipSuccess ? QMG_OK : hip_err(c, e, "graph launch");
+  }
+  // first use: run eagerly on the caller's stream (this also sizes every
+  // workspace buffer), then record the same sequence on the library's own
+  // stream (the caller's stream may be the legacy default stream, which
+  // cannot be captured); the recorded graph is later launched on `s`.
+  qmg_status st = vcycle_body(c, z, r, tau, nrhs, prm, nullptr, s, true);
+  if (st != QMG_OK) return st;
+  hipError_t e = hipSuccess;
+  if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c, e, "capture stream");
+  const uint64_t epoch = c->ws_epoch;
+  hipGraph_t graph = nullptr;
+  e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_err(c, e, "begin capture");
+  st = vcycle_body(c, z, r, tau, nrhs, prm, nullptr, c->cap_stream, true);
+  e = hipStreamEndCapture(c->cap_stream, &graph);
+  if (st != QMG_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_err(c, e, "end capture");
+  if (c->ws_epoch != epoch) {  // a buffer moved while recording: do not keep this graph
+    hipGraphDestroy(graph);
+    return set_err(c, QMG_E_HIP, "workspace changed during V-cycle capture");
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_err(c, e, "graph instantiate");
+  c->graphs[key] = exec;
+  return QMG_OK;
+}
+
+static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
+                              int* coarse_iters, hipStream_t s, bool graph_safe) {
   const int p = prm->mg_prec;
   const int64_t n = (int64_t)field_elems(c);
   void* rp = (void*)r;
@@ -278,8 +338,11 @@ qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, 
     e = launch_restrict(c, p, rc, rp, nrhs, s);
     if (e != hipSuccess) return hip_err(c, e, "restrict");
     int it = 0;
-    qmg_status st = solver_coarse_gmres(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, prm->coarse_tol, &it, s);
+    qmg_status st = graph_safe ? coarse_gmres_device(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, s)
+                               : solver_coarse_gmres(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, prm->coarse_tol,
+                                                     &it, s);
     if (st != QMG_OK) return st;
+    if (graph_safe) it = prm->coarse_maxiter;
     if (coarse_iters) *coarse_iters += it;
     e = launch_prolong(c, p, zp, yc, nrhs, s);
     if (e != hipSuccess) return hip_err(c, e, "prolong");
@@ -418,6 +481,7 @@ qmg_status build_mg(qmg_ctx* c, const void* W, int ntv, hipStream_t s) {
   const size_t del = (size_t)g.nb * 9 * nc * nc;
   c->have_mg = false;
   c->ntv = ntv;
+  drop_graphs(c);
   for (int p = 0; p < 3; ++p) {
     const std::string ps = std::to_string(p);
     c->P[p] = ws_get(c, "mg_P" + ps, pel * cbytes(p));

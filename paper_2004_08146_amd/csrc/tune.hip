@@ -54,6 +54,13 @@ bool load_cache(qmg_ctx* c, const std::string& path, const std::string& key) {
         ++found;
       }
     }
+  {
+    const std::string kc = "\"" + key + "|coarse_mfma\":";
+    const size_t pc = txt.find(kc);
+    int vc = -1;
+    if (pc != std::string::npos && std::sscanf(txt.c_str() + pc + kc.size(), " %d", &vc) == 1 && (vc == 0 || vc == 1))
+      c->tune.coarse_mfma = vc;
+  }
   const std::string ks = "\"" + key + "|sap\":";
   const size_t pos = txt.find(ks);
   int v = -1;
@@ -145,6 +152,35 @@ qmg_status tune_run(qmg_ctx* c, const char* path) {
     js << ",\n  \"" << key << "|sap|" << kPrecName[p] << "|ms\": [" << times.str() << "]";
   }
   if (st == QMG_OK) js << ",\n  \"" << key << "|sap\": " << c->tune.sap_variant;
+  // coarse apply: vector kernel vs MFMA kernel (needs the coarse operator)
+  for (int p = 0; p < 3 && st == QMG_OK && c->have_mg; ++p) {
+    const int n = 16;
+    const size_t bytes = coarse_elems(c) * cbytes(coarse_prec(p)) * n;
+    void* x = ws_get(c, "tune_in", bytes);
+    void* y = ws_get(c, "tune_out", bytes);
+    if (!x || !y) { st = set_err(c, QMG_E_NOMEM, "autotune: out of device memory"); break; }
+    hipError_t e = launch_fill_zero(x, bytes, s);
+    double best_ms = 1e30;
+    int best = c->tune.coarse_mfma;
+    std::ostringstream times;
+    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+      c->tune.coarse_mfma = v;
+      e = launch_coarse_apply(c, p, y, x, tau.data(), n, s);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch_coarse_apply(c, p, y, x, tau.data(), n, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      ms /= 5;
+      times << (v ? ", " : "") << ms;
+      if (ms < best_ms) { best_ms = ms; best = v; }
+    }
+    if (e != hipSuccess) { st = hip_err(c, e, "autotune coarse"); break; }
+    c->tune.coarse_mfma = best;
+    js << ",\n  \"" << key << "|coarse|" << kPrecName[p] << "|ms\": [" << times.str() << "]";
+  }
+  if (st == QMG_OK && c->have_mg) js << ",\n  \"" << key << "|coarse_mfma\": " << c->tune.coarse_mfma;
   js << "\n}\n";
   c->tune.force_variant = -1;
   hipEventDestroy(e0);

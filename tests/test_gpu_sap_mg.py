@@ -131,3 +131,55 @@ def test_rank_deficient_test_vectors_rejected():
     with pytest.raises(qmg.QmgError) as e:
         lat.set_test_vectors(lat.pack(dev(W)), 4)
     assert e.value.status == -5
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-11), ("f32", 2e-5)])
+def test_vcycle_graph_replays(prec, tol):
+    """The HIP-graph V-cycle (device-resident coarse GMRES, fixed steps): every replay,
+    with eager work and synchronisations in between, matches the oracle V-cycle."""
+    case("vcycle graph replays " + prec)
+    ntv = 8
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    qmg, lat, op, h, order = _mg(dims, block, ntv)
+    r = random_spinors(dims, 2, 43)
+    taus = [0.02, -0.1]
+    rg = lat.pack(dev(r))
+    prm = qmg.default_params(coarse_maxiter=10, coarse_tol=0.0, nu_post=2, n_mr=3, mg_prec=prec, use_graph=1)
+    prm0 = qmg.default_params(coarse_maxiter=10, coarse_tol=0.0, nu_post=2, n_mr=3, mg_prec=prec, use_graph=0)
+    ref = [h.vcycle(r[k], taus[k], 2, 3, 10, None) for k in range(2)]
+    eager = host(lat.unpack(lat.vcycle(lat.field(2), rg, taus, 2, prm0), 2))
+    z = lat.field(2)
+    for rep in range(4):
+        lat.vcycle(z, rg, taus, 2, prm)          # rep 0 runs eagerly and captures; later reps replay
+        got = host(lat.unpack(z, 2))
+        for k in range(2):
+            assert rel_err(got[k], ref[k]) < tol, (rep, k)
+            assert rel_err(got[k], eager[k]) < tol, (rep, k)
+        # unrelated eager work between replays
+        lat.apply_Q(lat.field(1), rg, 1)
+        torch.cuda.synchronize()
+        z.zero_()
+
+
+@pytest.mark.parametrize("ntv", [8, 24])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-5), ("bf16", 2e-2)])
+def test_coarse_apply_many_rhs(ntv, prec, tol):
+    """Coarse apply for ragged batches (5 and 17 rhs: the MFMA path, partial 16-rhs tiles).
+    FP32: each output sums 9 * 2 ntv = 432 products; rounding ~ sqrt(432) * 6e-8 ~ 1e-6 of the
+    largest entry, so 1e-5 bounds it with margin.  BF16 storage of D_c: 2^-8 per entry."""
+    case("coarse apply many rhs ntv=%d %s" % (ntv, prec))
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    qmg, lat, op, h, order = _mg(dims, block, ntv)
+    rng = np.random.default_rng(8)
+    cdt = np.complex128 if prec == "f64" else np.complex64
+    rdt = np.float64 if prec == "f64" else np.float32
+    for nrhs in (5, 17):
+        ylex = (rng.standard_normal((nrhs, len(order), 2 * ntv))
+                + 1j * rng.standard_normal((nrhs, len(order), 2 * ntv))).astype(cdt)
+        taus = [0.01 * (k - 3) for k in range(nrhs)]
+        yg = dev(lex_to_coarse(ylex, order).view(rdt))
+        og = lat.apply_coarse(lat.coarse(nrhs, prec), yg, taus, nrhs, prec)
+        out = coarse_to_lex(host(og).view(cdt), order, ntv)
+        for k in range(nrhs):
+            ref = h.coarse.apply(ylex[k].astype(np.complex128), taus[k])
+            assert rel_err(out[k], ref) < tol, (nrhs, k)

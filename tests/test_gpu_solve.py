@@ -34,10 +34,11 @@ def test_solve_sap_only_16x4():
     assert _true_relres_oracle(U, m0, C, host(lat.unpack(x))[0], b[0], tau) <= 1.5e-10
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-def test_solve_two_level_multishift(prec):
-    """8^4 lattice, 4^4 aggregates, setup-built test vectors, 4 shifts, V-cycle in prec, FP64 FGMRES."""
-    case("solve 8^4 two-level multishift " + prec)
+@pytest.mark.parametrize("prec,graph", [("f64", 0), ("f32", 0), ("bf16", 0), ("f32", 1)])
+def test_solve_two_level_multishift(prec, graph):
+    """8^4 lattice, 4^4 aggregates, setup-built test vectors, 4 shifts, V-cycle in prec
+    (optionally replayed as a HIP graph), FP64 FGMRES."""
+    case("solve 8^4 two-level multishift %s graph=%d" % (prec, graph))
     qmg = need_gpu()
     dims = (8, 8, 8, 8)
     U = random_links(dims, 0.5, seed_for(4, "U"))
@@ -51,7 +52,8 @@ def test_solve_two_level_multishift(prec):
     taus = [0.005 * (2 * k - 3) for k in range(nrhs)]
     b = random_spinors(dims, nrhs, seed_for(4, "b"))
     x = lat.field(nrhs)
-    prm = qmg.default_params(mg_prec=prec, restart=16, maxiter=300)
+    prm = qmg.default_params(mg_prec=prec, restart=16, maxiter=300, use_graph=graph,
+                             coarse_maxiter=8 if graph else 50)
     st, stats = lat.solve_shifted(x, lat.pack(dev(b)), taus, nrhs, prm)
     assert st == 0
     xs = host(lat.unpack(x, nrhs))
