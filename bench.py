@@ -147,7 +147,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dims", type=str, default="64,32,32,32")
     ap.add_argument("--nrhs", type=int, default=16)
-    ap.add_argument("--m0", type=float, default=-0.8)
+    ap.add_argument("--m0", type=float, default=None,
+                    help="bare mass (default: the near-critical value in tests/golden/m0_critical.json)")
     ap.add_argument("--setup-iters", type=int, default=4)
     ap.add_argument("--restart", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
@@ -168,6 +169,9 @@ def main():
     from synth import device_gaussian_spinors, random_links, random_spinors, seed_for, unit_links
 
     dims = tuple(int(v) for v in args.dims.split(","))
+    if args.m0 is None:
+        with open(os.path.join(ROOT, "tests", "golden", "m0_critical.json")) as fh:
+            args.m0 = float(json.load(fh)["m0"])
     if args.mode == "kernels":
         return kernels_mode(args, dims, torch, qmg, unit_links)
     V = int(np.prod(dims))

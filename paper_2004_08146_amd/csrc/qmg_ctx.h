@@ -28,9 +28,10 @@ struct Tune {
   int dslash[3][2] = {{1, 1}, {1, 1}, {1, 1}};  // [prec][nrhs == 1 ? 0 : 1] -> variant index
   int dslash_xcd_remap = 1;                      // XCD-aware mapping of work-groups to blocks
   int force_variant = -1;                        // >= 0: use this stencil variant (tuning, tests)
-  int sap_variant = 1;                           // 0 generic SAP; 1 LDS-staged 4^4 SAP (FP32 / BF16)
+  int sap_variant = 2;  // 0 generic SAP; 1, 2: LDS-staged 4^4 SAP (FP32 / BF16) with 1 or 2 rhs per work-group
   int coarse_rhs_tile = 4;                       // right-hand sides per coarse-apply work-group
   int coarse_mfma = 1;                           // MFMA coarse apply for many right-hand sides
+  int transfer_mr = 1;                           // restrict / prolong kernels sharing P loads across rhs
   int coarse_mfma_min_rhs = 4;                   // smallest batch that takes the MFMA path
   bool tuned = false;
 };

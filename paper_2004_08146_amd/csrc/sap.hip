@@ -353,19 +353,39 @@ __device__ __forceinline__ Spinor<float> diag_reg(const cpx<float> (&dg)[2][18],
   return o;
 }
 
-template <typename S, bool CLOVER>
-__global__ __launch_bounds__(256) void k_sap44(SapArgs<S> a) {
+// sum of 3 values over the 256 threads of one rhs slot (waves 4q..4q+3)
+__device__ __forceinline__ void slot_sum3(float (&v)[3], float* red, int slot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) red[wave * 3 + i] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float t = red[(4 * slot) * 3 + i];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) t += red[(4 * slot + q) * 3 + i];
+    v[i] = t;
+  }
+  __syncthreads();
+}
+
+template <typename S, bool CLOVER, int NS>
+__global__ __launch_bounds__(256 * NS) void k_sap44(SapArgs<S> a) {
   using P = typename PT<S>::stor;
   __shared__ cpx<float> Ul[36 * 256];
-  __shared__ cpx<float> rh[12 * 256];
-  __shared__ float red[16];
+  __shared__ cpx<float> rhs_lds[NS][12 * 256];
+  __shared__ float red[4 * NS * 3];
   const int w = blockIdx.x, nw = gridDim.x;
   const int L = ((nw & 7) == 0) ? (w & 7) * (nw >> 3) + (w >> 3) : w;
   const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(a.first_block + L);
-  const uint32_t l = threadIdx.x;
+  const uint32_t l = threadIdx.x & 255u;
+  const int slot = (int)(threadIdx.x >> 8);
+  cpx<float>* rh = rhs_lds[slot];
   const int* nbr = a.g.nbr;
-#pragma unroll 4
-  for (int i = 0; i < 36; ++i) {
+  for (int i = slot; i < 36; i += NS) {
     auto v = cv(ldo(a.U, ((b * 36u + (uint32_t)i) << 8) + l));
     Ul[i * 256 + l] = cpx<float>{float(v.re), float(v.im)};
   }
@@ -382,7 +402,11 @@ __global__ __launch_bounds__(256) void k_sap44(SapArgs<S> a) {
   const float mass4 = float(a.mass4);
   __syncthreads();
 #pragma unroll 1
-  for (int k = 0; k < a.nrhs; ++k) {
+  for (int k0 = 0; k0 < a.nrhs; k0 += NS) {
+    // both slots run every iteration (the barriers are work-group wide); a
+    // slot past the last rhs recomputes rhs k0 and does not store
+    const bool active = k0 + slot < a.nrhs;
+    const int k = active ? k0 + slot : k0;
     P* x = a.x + (size_t)k * a.fstride;
     const P* f = a.f + (size_t)k * a.fstride;
     const float tau = float(a.tau[k]);
@@ -450,7 +474,7 @@ __global__ __launch_bounds__(256) void k_sap44(SapArgs<S> a) {
           v[1] += t.im;
           v[2] += norm2(q.s[s][c]);
         }
-      block_sum<float, 3>(v, red);
+      slot_sum3(v, red, slot);
       cpx<float> alpha = czero<float>();
       if (v[2] > 0.f) alpha = cpx<float>{v[0] / v[2], v[1] / v[2]};
 #pragma unroll
@@ -461,11 +485,15 @@ __global__ __launch_bounds__(256) void k_sap44(SapArgs<S> a) {
           rho.s[s][c] = rho.s[s][c] - alpha * q.s[s][c];
         }
     }
+    if (active) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+      for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        sto(x, ((b * 12u + (uint32_t)(3 * s + c)) << 8) + l, vc(xs.s[s][c], (P*)nullptr));
+        for (int c = 0; c < 3; ++c)
+          sto(x, ((b * 12u + (uint32_t)(3 * s + c)) << 8) + l, vc(xs.s[s][c], (P*)nullptr));
+    }
+    // the residual of the next rhs reads x of neighbouring blocks only, and
+    // this work-group's own block is rewritten by this work-group alone
   }
 }
 
@@ -491,10 +519,15 @@ void launch_s(const qmg_ctx* c, int p, void* x, const void* f, const double* tau
   size_t lds = sizeof(cpx<R>) * 12 * bs + sizeof(R) * 3 * std::max(bs, 8);
   const bool b44 = c->g.block[0] == 4 && c->g.block[1] == 4 && c->g.block[2] == 4 && c->g.block[3] == 4;
   if constexpr (!std::is_same<S, double>::value) {
-    if (b44 && c->tune.sap_variant == 1) {
+    if (b44 && c->tune.sap_variant >= 1) {
       dim3 grid((unsigned)a.nblk);
-      if (c->clover) hipLaunchKernelGGL((k_sap44<S, true>), grid, dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((k_sap44<S, false>), grid, dim3(256), 0, s, a);
+      if (c->tune.sap_variant == 2) {
+        if (c->clover) hipLaunchKernelGGL((k_sap44<S, true, 2>), grid, dim3(512), 0, s, a);
+        else hipLaunchKernelGGL((k_sap44<S, false, 2>), grid, dim3(512), 0, s, a);
+      } else {
+        if (c->clover) hipLaunchKernelGGL((k_sap44<S, true, 1>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_sap44<S, false, 1>), grid, dim3(256), 0, s, a);
+      }
       return;
     }
   }

@@ -117,12 +117,101 @@ __global__ __launch_bounds__(256) void k_prolong(Geom g, typename PT<S>::stor* v
     }
 }
 
+// ---- many right-hand sides: R rhs per work-group share every P load
+template <typename S, typename C, int R>
+__global__ __launch_bounds__(256) void k_restrict_mr(Geom g, typename PT<C>::stor* y, const typename PT<S>::stor* P,
+                                                     const typename PT<S>::stor* v, int ntv, int nrhs,
+                                                     int64_t fstride) {
+  using Rr = typename PT<S>::real;
+  extern __shared__ unsigned char smem_r[];
+  Rr* red = reinterpret_cast<Rr*>(smem_r);
+  const int ng = (nrhs + R - 1) / R;
+  const int b = blockIdx.x / ng, k0 = (blockIdx.x % ng) * R, l = threadIdx.x;
+  const int nr = nrhs - k0 < R ? nrhs - k0 : R;
+  const int nc = 2 * ntv;
+  cpx<Rr> vv[R][12];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < 12; ++c)
+      vv[r][c] = r < nr ? ldcv<Rr>(v + (int64_t)(k0 + r) * fstride, sidx(g, b, c, l)) : czero<Rr>();
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    for (int j0 = 0; j0 < ntv; j0 += 4) {
+      Rr acc[8 * R];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = j0 + t;
+        cpx<Rr> pv[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) pv[d] = j < ntv ? ldcv<Rr>(P, pidx(g, ntv, b, h, j, d, l)) : czero<Rr>();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          cpx<Rr> sum = czero<Rr>();
+#pragma unroll
+          for (int d = 0; d < 6; ++d) sum = sum + cmul_conj(pv[d], vv[r][6 * h + d]);
+          acc[(r * 4 + t) * 2] = sum.re;
+          acc[(r * 4 + t) * 2 + 1] = sum.im;
+        }
+      }
+      wg_sum<Rr, 8 * R>(acc, red);
+      if (l < 4 * R) {
+        const int r = l / 4, t = l % 4;
+        Rr re = acc[0], im = acc[1];
+#pragma unroll
+        for (int q = 1; q < 4 * R; ++q)
+          if (q == l) { re = acc[2 * q]; im = acc[2 * q + 1]; }
+        if (r < nr && j0 + t < ntv) stcv(y + ((int64_t)(k0 + r) * g.nb + b) * nc, h * ntv + j0 + t, cpx<Rr>{re, im});
+      }
+    }
+}
+
+// P read once per site for every rhs: the coarse inputs of the block live in LDS
+template <typename S, typename C>
+__global__ __launch_bounds__(256) void k_prolong_mr(Geom g, typename PT<S>::stor* v, const typename PT<S>::stor* P,
+                                                    const typename PT<C>::stor* y, int ntv, int nrhs, int64_t fstride) {
+  using R = typename PT<S>::real;
+  __shared__ cpx<R> ys[QMG_MAXRHS * 64];
+  const int b = blockIdx.x, l = threadIdx.x;
+  const int nc = 2 * ntv;
+  for (int o = l; o < nrhs * nc; o += blockDim.x) {
+    const int k = o / nc, i = o % nc;
+    ys[k * 64 + i] = ldcv<R>(y + ((int64_t)k * g.nb + b) * nc, i);
+  }
+  __syncthreads();
+  for (int h = 0; h < 2; ++h)
+    for (int d = 0; d < 6; ++d) {
+      cpx<R> pc[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) pc[j] = j < ntv ? ldcv<R>(P, pidx(g, ntv, b, h, j, d, l)) : czero<R>();
+      for (int k = 0; k < nrhs; ++k) {
+        cpx<R> s = czero<R>();
+#pragma unroll
+        for (int j = 0; j < 32; ++j)
+          if (j < ntv) s = s + pc[j] * ys[k * 64 + h * ntv + j];
+        stcv(v + (int64_t)k * fstride, sidx(g, b, 6 * h + d, l), s);
+      }
+    }
+}
+
 template <typename S>
 void restrict_t(const qmg_ctx* c, void* yc, const void* v, int nrhs, hipStream_t s, int p) {
   using P = typename PT<S>::stor;
   using R = typename PT<S>::real;
   const int bs = 1 << c->g.bs_log;
   size_t lds = sizeof(R) * 16 * std::max(bs, 4);
+  if (nrhs > 1 && c->tune.transfer_mr) {
+    constexpr int RR = std::is_same<S, double>::value ? 2 : 4;
+    const int ng = (nrhs + RR - 1) / RR;
+    const size_t lds2 = sizeof(R) * 8 * RR * std::max(bs, 4);
+    if (p == QMG_F64)
+      hipLaunchKernelGGL((k_restrict_mr<S, double, RR>), dim3(c->g.nb * ng), dim3(bs), lds2, s, c->g, (double2*)yc,
+                         (const P*)c->P[p], (const P*)v, c->ntv, nrhs, (int64_t)field_elems(c));
+    else
+      hipLaunchKernelGGL((k_restrict_mr<S, float, RR>), dim3(c->g.nb * ng), dim3(bs), lds2, s, c->g, (float2*)yc,
+                         (const P*)c->P[p], (const P*)v, c->ntv, nrhs, (int64_t)field_elems(c));
+    return;
+  }
   if (p == QMG_F64)
     hipLaunchKernelGGL((k_restrict<S, double>), dim3(c->g.nb * nrhs), dim3(bs), lds, s, c->g, (double2*)yc,
                        (const P*)c->P[p], (const P*)v, c->ntv, nrhs, (int64_t)field_elems(c),
@@ -137,6 +226,15 @@ template <typename S>
 void prolong_t(const qmg_ctx* c, void* v, const void* yc, int nrhs, hipStream_t s, int p) {
   using P = typename PT<S>::stor;
   const int bs = 1 << c->g.bs_log;
+  if (nrhs > 1 && c->tune.transfer_mr) {
+    if (p == QMG_F64)
+      hipLaunchKernelGGL((k_prolong_mr<S, double>), dim3(c->g.nb), dim3(bs), 0, s, c->g, (P*)v, (const P*)c->P[p],
+                         (const double2*)yc, c->ntv, nrhs, (int64_t)field_elems(c));
+    else
+      hipLaunchKernelGGL((k_prolong_mr<S, float>), dim3(c->g.nb), dim3(bs), 0, s, c->g, (P*)v, (const P*)c->P[p],
+                         (const float2*)yc, c->ntv, nrhs, (int64_t)field_elems(c));
+    return;
+  }
   if (p == QMG_F64)
     hipLaunchKernelGGL((k_prolong<S, double>), dim3(c->g.nb * nrhs), dim3(bs), 0, s, c->g, (P*)v,
                        (const P*)c->P[p], (const double2*)yc, c->ntv, nrhs, (int64_t)field_elems(c));

@@ -64,7 +64,7 @@ bool load_cache(qmg_ctx* c, const std::string& path, const std::string& key) {
   const std::string ks = "\"" + key + "|sap\":";
   const size_t pos = txt.find(ks);
   int v = -1;
-  if (pos != std::string::npos && std::sscanf(txt.c_str() + pos + ks.size(), " %d", &v) == 1 && (v == 0 || v == 1))
+  if (pos != std::string::npos && std::sscanf(txt.c_str() + pos + ks.size(), " %d", &v) == 1 && v >= 0 && v <= 2)
     c->tune.sap_variant = v;
   return found == 6;
 }
@@ -134,7 +134,7 @@ qmg_status tune_run(qmg_ctx* c, const char* path) {
     double best_ms = 1e30;
     int best = sap_default;
     std::ostringstream times;
-    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+    for (int v = 0; v < 3 && e == hipSuccess; ++v) {
       c->tune.sap_variant = v;
       e = launch_sap_colour(c, p, x, f, tau.data(), n, 0, 3, s);
       if (e == hipSuccess) e = hipEventRecord(e0, s);

@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from gpu_common import case, coarse_to_lex, dev, host, lex_to_coarse, need_gpu, torch
+from gpu_common import case, coarse_to_lex, dev, host, lex_to_coarse, need_gpu, torch  # noqa: F401
 from helpers import rel_err
 from oracle import clover as oclover
 from oracle import dirac, krylov, mg, sap
@@ -46,7 +46,7 @@ def _force_sap(lat, tmp_path, dims, block, clover, v):
     lat.autotune(str(path))
 
 
-@pytest.mark.parametrize("sapv", [0, 1])
+@pytest.mark.parametrize("sapv", [0, 1, 2])
 @pytest.mark.parametrize("prec,tol", [("f32", 2e-5), ("bf16", 5e-2)])
 def test_sap_reduced_precision(prec, tol, sapv, tmp_path):
     """FP32 / BF16-storage SAP (both kernels: generic and LDS-staged 4^4) on 2 rhs."""
@@ -183,3 +183,104 @@ def test_coarse_apply_many_rhs(ntv, prec, tol):
         for k in range(nrhs):
             ref = h.coarse.apply(ylex[k].astype(np.complex128), taus[k])
             assert rel_err(out[k], ref) < tol, (nrhs, k)
+
+
+def _block_window(U, f, X, block, csw, nwin=4):
+    """Periodic window of nwin blocks per direction holding block X of the big lattice at
+    window position p (1 or 2 per direction, so its 8 neighbouring blocks are inside); the
+    origin sits on an even block offset so window and lattice colours agree.  The clover term
+    is computed on the window plus a one-site margin (its leaves reach one site out), so no
+    value the sampled block depends on sees the window's own periodic wrap.
+    Returns (U, clover, f, inner slice) of the window."""
+    dims = U.shape[:4]
+    idx, idx_m, inner = [], [], []
+    for mu in range(4):
+        p = 1 if X[mu] % 2 else 2
+        start = (X[mu] - p) * block[mu]
+        idx.append((start + np.arange(nwin * block[mu])) % dims[mu])
+        idx_m.append((start - 1 + np.arange(nwin * block[mu] + 2)) % dims[mu])
+        inner.append(slice(p * block[mu], (p + 1) * block[mu]))
+    Cm = oclover.clover_term(U[np.ix_(*idx_m)], csw)
+    C = Cm[1:-1, 1:-1, 1:-1, 1:-1]
+    sl = np.ix_(*idx)
+    return U[sl], C, f[sl], tuple(inner)
+
+
+def test_full_size_sap_and_restrict_sampled():
+    """64x32^3, c_sw = 1, 16 rhs batch layout of the bench: one FP64 SAP sweep from x = 0 and the
+    restriction, checked on sampled blocks.  For a colour-1 block the sweep depends only on f in the
+    block and its 8 neighbouring colour-0 blocks, so a 4^4-block window reproduces it exactly."""
+    from gpu_common import big_inputs
+    case("full-size SAP / restrict sampled")
+    qmg = need_gpu()
+    dims, block = (64, 32, 32, 32), (4, 4, 4, 4)
+    U, f = big_inputs(dims, 0.5, 5, 2)
+    m0, csw, tau = -0.8, 1.0, 0.0125
+    lat = qmg.Lattice(dims, block)
+    lat.set_gauge(dev(U), m0, csw)
+    fg = lat.pack(dev(f))
+    xg = lat.field(2)
+    lat.sap_smooth(xg, fg, [tau, tau], 2, nsweep=1, n_mr=3)
+    xs = lat.unpack(xg, 2)
+    rng = np.random.default_rng(12)
+    nbk = [d // b for d, b in zip(dims, block)]
+    done = 0
+    while done < 2:
+        X = [int(rng.integers(0, n)) for n in nbk]
+        if sum(X) % 2 != 1:   # colour-1 block: its residual reads the colour-0 neighbours
+            continue
+        Uw, C, fw, inner = _block_window(U, f[0], X, block, csw)
+        ref = sap.sap(dirac.Operator(Uw, m0, C), fw, np.zeros_like(fw), tau, block, 1, 3)[inner]
+        sl = tuple(slice(X[mu] * block[mu], (X[mu] + 1) * block[mu]) for mu in range(4))
+        got = host(xs[0][sl])
+        assert rel_err(got, ref) < 1e-12
+        done += 1
+    # restriction: the aggregate of block b only sees P_b (built from W on block b) and v on block b
+    ntv = 24
+    W = random_test_vectors(dims, ntv, seed_for(5, "W"))
+    lat.set_test_vectors(lat.pack(dev(W)), ntv)
+    order = lat.coarse_site_order()
+    yc = coarse_to_lex(host(lat.restrict(lat.coarse(2), fg, 2)).view(np.complex128), order, ntv)
+    for _ in range(3):
+        X = [int(rng.integers(0, n)) for n in nbk]
+        sl = tuple(slice(X[mu] * block[mu], (X[mu] + 1) * block[mu]) for mu in range(4))
+        Pb = mg.build_P([w[sl] for w in W], block)
+        ref = mg.restrict(Pb, f[1][sl], block)[0]
+        lex = ((X[0] * nbk[1] + X[1]) * nbk[2] + X[2]) * nbk[3] + X[3]
+        assert rel_err(yc[1][lex], ref) < 1e-13
+    # coarse operator, any size: Q_c = Gamma5^c D_c is Hermitian, <u, Q_c v> = <Q_c u, v>
+    nc = 2 * ntv
+    u = (rng.standard_normal((len(order), nc)) + 1j * rng.standard_normal((len(order), nc)))
+    v = (rng.standard_normal((len(order), nc)) + 1j * rng.standard_normal((len(order), nc)))
+    g5 = np.concatenate([np.ones(ntv), -np.ones(ntv)])
+    Du = host(lat.apply_coarse(lat.coarse(1), dev(u.view(np.float64)), [0.0])).view(np.complex128).reshape(u.shape)
+    Dv = host(lat.apply_coarse(lat.coarse(1), dev(v.view(np.float64)), [0.0])).view(np.complex128).reshape(v.shape)
+    a = np.vdot(u, g5 * Dv)
+    b = np.vdot(g5 * Du, v)
+    assert abs(a - b) < 1e-12 * abs(a)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 2e-6)])
+def test_restrict_prolong_ragged_batches(prec, tol):
+    """Restriction / prolongation kernels that share P loads across right-hand sides,
+    on ragged batches (1, 5, 7 rhs) with 24 test vectors."""
+    case("restrict/prolong ragged " + prec)
+    ntv = 24
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    qmg, lat, op, h, order = _mg(dims, block, ntv)
+    cdt = np.complex128 if prec == "f64" else np.complex64
+    rdt = np.float64 if prec == "f64" else np.float32
+    rng = np.random.default_rng(21)
+    for nrhs in (1, 5, 7):
+        v = random_spinors(dims, nrhs, 100 + nrhs)
+        vg = lat.pack(dev(v), prec)
+        vin = host(lat.unpack(vg, nrhs, prec))
+        y = coarse_to_lex(host(lat.restrict(lat.coarse(nrhs, prec), vg, nrhs, prec)).view(cdt), order, ntv)
+        for k in range(nrhs):
+            assert rel_err(y[k], mg.restrict(h.P, vin[k], block)) < tol, (nrhs, k)
+        ylex = (rng.standard_normal((nrhs, len(order), 2 * ntv))
+                + 1j * rng.standard_normal((nrhs, len(order), 2 * ntv))).astype(cdt)
+        pv = host(lat.unpack(lat.prolong(lat.field(nrhs, prec), dev(lex_to_coarse(ylex, order).view(rdt)), nrhs,
+                                         prec), nrhs, prec))
+        for k in range(nrhs):
+            assert rel_err(pv[k], mg.prolong(h.P, ylex[k].astype(np.complex128), dims, block)) < tol, (nrhs, k)
