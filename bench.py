@@ -1,9 +1,10 @@
 """Benchmark of the shifted-solve hot path on one MI355X.
 
 Workload (config 5): 64x32^3 lattice, clover c_sw = 1.0, synthetic links
-exp(i*0.5*H), 16 right-hand sides with shifts tau_k = 0.0025*(2k - 15),
-two-level multigrid (4^4 aggregates, 24 test vectors from the adaptive setup),
-FP64 FGMRES to a 1e-10 true relative residual.
+exp(i*0.5*H), near-critical bare mass (m0 = -0.95 from tests/golden/
+m0_critical.json), 16 right-hand sides with shifts tau_k = 0.001*(2k - 15),
+two-level multigrid (4^4 aggregates, 24 test vectors, 6 setup iterations),
+FP64 FGMRES(8) to a 1e-10 true relative residual.
 
 A step is one batched shifted solve of the 16 right-hand sides with the
 mixed-precision (FP32) V-cycle -- every kernel of the path (stencil, SAP,
@@ -110,6 +111,15 @@ def kernels_mode(args, dims, torch, qmg, unit_links):
     lat.set_gauge(torch.from_numpy(unit_links(dims)).cuda(), args.m0, 1.0)
     if args.tune_cache:
         lat.autotune(args.tune_cache)
+    if args.variant is not None:
+        # pin one stencil variant (and the XCD remap) for counter runs
+        key = "gfx950|%s|4x4x4x4|clover=1" % "x".join(map(str, dims))
+        path = "/tmp/qmg_pin_%d.json" % os.getpid()
+        with open(path, "w") as fh:
+            ent = ['"%s|dslash|%s|%d": %d' % (key, p, c, args.variant) for p in ("f64", "f32", "bf16") for c in (0, 1)]
+            ent.append('"%s|xcd_remap": %d' % (key, args.remap))
+            fh.write("{\n" + ",\n".join(ent) + "\n}\n")
+        lat.autotune(path)
     timer = EventTimer(torch)
     taus = [0.0] * nrhs
     out = {}
@@ -149,13 +159,17 @@ def main():
     ap.add_argument("--nrhs", type=int, default=16)
     ap.add_argument("--m0", type=float, default=None,
                     help="bare mass (default: the near-critical value in tests/golden/m0_critical.json)")
-    ap.add_argument("--setup-iters", type=int, default=4)
+    ap.add_argument("--setup-iters", type=int, default=6)
+    ap.add_argument("--dtau", type=float, default=0.001, help="shift spacing: tau_k = dtau*(2k - nrhs + 1)")
+    ap.add_argument("--maxiter", type=int, default=500)
     ap.add_argument("--restart", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the extra FP64/BF16 solves")
     ap.add_argument("--tune-cache", type=str, default=None, help="autotuner JSON cache (default: fresh)")
     ap.add_argument("--graph", type=int, default=1, help="1: V-cycle replayed as a HIP graph (fixed coarse steps)")
     ap.add_argument("--coarse-iters", type=int, default=4, help="coarse GMRES steps in graph mode")
+    ap.add_argument("--variant", type=int, default=None, help="kernels mode: pin this stencil variant")
+    ap.add_argument("--remap", type=int, default=1, help="kernels mode: XCD-aware work-group mapping (with --variant)")
     ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",
                     help="kernels: only a few launches of the hot kernels and a 1 GiB copy (for counter runs)")
     args = ap.parse_args()
@@ -177,7 +191,7 @@ def main():
     V = int(np.prod(dims))
     nrhs = args.nrhs
     csw, m0 = 1.0, args.m0
-    taus = [0.0025 * (2 * k - 15) for k in range(nrhs)]
+    taus = [args.dtau * (2 * k - (nrhs - 1)) for k in range(nrhs)]
     timer = EventTimer(torch)
 
     t0 = time.time()
@@ -205,7 +219,7 @@ def main():
 
     def solve(prec, graph=args.graph):
         x = lat.field(nrhs)
-        prm = qmg.default_params(mg_prec=prec, restart=args.restart, maxiter=2000, use_graph=graph,
+        prm = qmg.default_params(mg_prec=prec, restart=args.restart, maxiter=args.maxiter, use_graph=graph,
                                  coarse_maxiter=args.coarse_iters if graph else 50)
         st, stats = lat.solve_shifted(x, bg, taus, nrhs, prm)
         return st, stats
@@ -217,9 +231,10 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     all_stats = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         st, stats = solve("f32")
         all_stats.append((st, stats))
+        print("[bench] step %d done: status %d" % (i, st), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = 1000.0 * dt / args.steps
@@ -269,7 +284,8 @@ def main():
                 "achieved": dom["gbps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": dom["gbps"] / HBM_PEAK_GBS, "traffic": None}
 
-    applies = float(np.mean([s["iters"] * 13 + s["restarts"] + 1 for s in all_stats[-1][1]]))
+    # fine-operator applications per rhs: FGMRES apply + nu * (1 residual + n_MR block applies)
+    applies = float(np.mean([s["iters"] * (1 + 3 * 4) + s["restarts"] + 1 for s in all_stats[-1][1]]))
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(U, b[0], m0, csw, taus[0], applies)
@@ -284,6 +300,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "64x32^3 clover shifted solve, 16 rhs, two-level MG, FGMRES to 1e-10",
                    "dims": list(dims), "csw": csw, "m0": m0, "nrhs": nrhs, "taus": [taus[0], taus[-1]],
+                   "dtau": args.dtau,
                    "block": [4, 4, 4, 4], "ntv": ntv, "restart": args.restart, "setup_iters": args.setup_iters},
         "converged": ok, "max_true_relres": relres, "fgmres_iters": iters, "setup_s": setup_s,
         "solve_ms": {"mixed_f32": ms_step, **{"%s_precond" % k: v["ms"] for k, v in extra.items()}},

@@ -55,6 +55,13 @@ bool load_cache(qmg_ctx* c, const std::string& path, const std::string& key) {
       }
     }
   {
+    const std::string kr = "\"" + key + "|xcd_remap\":";
+    const size_t pr = txt.find(kr);
+    int vr = -1;
+    if (pr != std::string::npos && std::sscanf(txt.c_str() + pr + kr.size(), " %d", &vr) == 1 && (vr == 0 || vr == 1))
+      c->tune.dslash_xcd_remap = vr;
+  }
+  {
     const std::string kc = "\"" + key + "|coarse_mfma\":";
     const size_t pc = txt.find(kc);
     int vc = -1;
