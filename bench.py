@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the extra FP64/BF16 solves")
     ap.add_argument("--tune-cache", type=str, default=None, help="autotuner JSON cache (default: fresh)")
     ap.add_argument("--graph", type=int, default=1, help="1: V-cycle replayed as a HIP graph (fixed coarse steps)")
-    ap.add_argument("--coarse-iters", type=int, default=4, help="coarse GMRES steps in graph mode")
+    ap.add_argument("--coarse-iters", type=int, default=16, help="coarse GMRES steps in graph mode")
     ap.add_argument("--variant", type=int, default=None, help="kernels mode: pin this stencil variant")
     ap.add_argument("--remap", type=int, default=1, help="kernels mode: XCD-aware work-group mapping (with --variant)")
     ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",

@@ -1,6 +1,8 @@
 // Device-resident GMRES scalars (Hessenberg column, Givens rotations,
 // back-substitution) so a fixed-step coarse GMRES -- and with it the whole
 // V-cycle -- runs without host round trips and can be captured in a HIP graph.
+// Being part of the preconditioner, this coarse GMRES makes a single classical
+// Gram-Schmidt pass per step (no data-dependent second pass).
 // One thread per right-hand side; the rotations follow the same convention as
 // the host solver: [[c, s], [-conj(s), c]] [a; b] = [r; 0], c real.
 #include "qmg_ctx.h"
@@ -140,7 +142,7 @@ qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const 
   for (int j = 0; j < m && e == hipSuccess; ++j) {
     char* Vj = (char*)V + (size_t)j * bb;
     e = launch_coarse_apply(c, p, w, Vj, tau, nrhs, s);
-    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+    for (int pass = 0; pass < 1 && e == hipSuccess; ++pass) {
       e = launch_multidot(cp, dots, V, vs, j + 1, w, n, n, nrhs, part, s, 0);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_gm_coef, g1, b1, 0, s, st, dots, coef, j, nrhs);

@@ -73,6 +73,9 @@ struct Lsq {
   }
 };
 
+// squared norm ratio below which a second Gram-Schmidt pass is made
+constexpr double kReorthRatio2 = 0.05 * 0.05;
+
 double* host_buf(qmg_ctx* c, const std::string& name, size_t ndouble) {
   auto& v = c->hbuf[name];
   if (v.size() < ndouble) v.resize(ndouble);
@@ -141,9 +144,11 @@ struct Space {
     return QMG_OK;
   }
   // One Arnoldi step on basis V_0..V_j with new vector w; h[k] gets j+2 entries.
-  // Classical Gram-Schmidt with the DGKS criterion: a second pass is made when
-  // the projection removed more than half of the squared norm of some column
-  // (||w_new|| < ||w|| / sqrt(2)); the new norm comes out of the update pass.
+  // Classical Gram-Schmidt with a DGKS-type test: a second pass is made when the
+  // projection cancelled so much of some column that ||w_new|| < 0.05 ||w||.
+  // One pass leaves an orthogonality error of about eps ||w|| / ||w_new||
+  // (<= 20 eps here); the true residual is recomputed after every restart
+  // cycle anyway.  The new norm comes out of the update pass.
   qmg_status arnoldi(std::vector<std::vector<cd>>& h, void* V, int j, void* w) {
     const int J = j + 1;
     h.assign(nrhs, std::vector<cd>(j + 2, cd(0)));
@@ -179,7 +184,7 @@ struct Space {
         after[k] = hd[2 * k];
         if (!std::isfinite(after[k]) || !std::isfinite(before[k]))
           return set_err(c, QMG_E_NUMERIC, "non-finite norm in Arnoldi step");
-        if (after[k] < 0.5 * before[k]) again = true;
+        if (after[k] < kReorthRatio2 * before[k]) again = true;
         before[k] = after[k];
       }
       if (!again) break;
