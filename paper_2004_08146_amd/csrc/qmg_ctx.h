@@ -32,6 +32,7 @@ struct Tune {
   int coarse_rhs_tile = 4;                       // right-hand sides per coarse-apply work-group
   int coarse_mfma = 1;                           // MFMA coarse apply for many right-hand sides
   int transfer_mr = 1;                           // restrict / prolong kernels sharing P loads across rhs
+  int restrict_mfma_min_rhs = 4;                 // restriction on MFMA from this many rhs (1000: never)
   int coarse_mfma_min_rhs = 4;                   // smallest batch that takes the MFMA path
   bool tuned = false;
 };

@@ -353,7 +353,10 @@ __device__ __forceinline__ Spinor<float> diag_reg(const cpx<float> (&dg)[2][18],
   return o;
 }
 
-// sum of 3 values over the 256 threads of one rhs slot (waves 4q..4q+3)
+// sum of 3 values over the 256 threads of one rhs slot (waves 4q..4q+3).
+// red is double buffered by the caller (alternate halves on successive calls),
+// so one barrier suffices: a half is rewritten only two calls later, after
+// every thread has passed the next call's barrier.
 __device__ __forceinline__ void slot_sum3(float (&v)[3], float* red, int slot) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -369,7 +372,6 @@ __device__ __forceinline__ void slot_sum3(float (&v)[3], float* red, int slot) {
     for (int q = 1; q < 4; ++q) t += red[(4 * slot + q) * 3 + i];
     v[i] = t;
   }
-  __syncthreads();
 }
 
 template <typename S, bool CLOVER, int NS>
@@ -377,7 +379,8 @@ __global__ __launch_bounds__(256 * NS) void k_sap44(SapArgs<S> a) {
   using P = typename PT<S>::stor;
   __shared__ cpx<float> Ul[36 * 256];
   __shared__ cpx<float> rhs_lds[NS][12 * 256];
-  __shared__ float red[4 * NS * 3];
+  __shared__ float red[2][4 * NS * 3];
+  int rb = 0;
   const int w = blockIdx.x, nw = gridDim.x;
   const int L = ((nw & 7) == 0) ? (w & 7) * (nw >> 3) + (w >> 3) : w;
   const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(a.first_block + L);
@@ -474,7 +477,8 @@ __global__ __launch_bounds__(256 * NS) void k_sap44(SapArgs<S> a) {
           v[1] += t.im;
           v[2] += norm2(q.s[s][c]);
         }
-      slot_sum3(v, red, slot);
+      slot_sum3(v, red[rb], slot);
+      rb ^= 1;
       cpx<float> alpha = czero<float>();
       if (v[2] > 0.f) alpha = cpx<float>{v[0] / v[2], v[1] / v[2]};
 #pragma unroll

@@ -194,12 +194,103 @@ __global__ __launch_bounds__(256) void k_prolong_mr(Geom g, typename PT<S>::stor
     }
 }
 
+// ---- restriction on MFMA: per block and chirality h, Y_h (ntv x 16 rhs) =
+// P_h^H (ntv x K) V_h (K x 16), K = 6 * 256 (spin-in-half, colour, site),
+// as four real 16x16x4 products per k-step.  One wave per chirality; the 4 k
+// values of a step are 4 consecutive sites with the same (spin, colour).
+typedef float tf4 __attribute__((ext_vector_type(4)));
+typedef double td4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ tf4 tmfma(float a, float b, tf4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ td4 tmfma(double a, double b, td4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+template <typename R> struct TAcc;
+template <> struct TAcc<float> { using T = tf4; };
+template <> struct TAcc<double> { using T = td4; };
+template <typename R> __device__ __forceinline__ int trow(int l, int r);
+template <> __device__ __forceinline__ int trow<float>(int l, int r) { return 4 * (l >> 4) + r; }
+template <> __device__ __forceinline__ int trow<double>(int l, int r) { return 4 * r + (l >> 4); }
+
+template <typename S, typename C, int MT>
+__global__ __launch_bounds__(128) void k_restrict_mfma(Geom g, typename PT<C>::stor* y, const typename PT<S>::stor* P,
+                                                       const typename PT<S>::stor* v, int ntv, int nrhs, int64_t fstride) {
+  using R = typename PT<S>::real;
+  using AT = typename TAcc<R>::T;
+  const int b = blockIdx.x, n0 = blockIdx.y * 16;
+  const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ln = lane & 15, lk = lane >> 4;
+  const int n = n0 + ln;
+  const bool nok = n < nrhs;
+  const auto* vn = v + (int64_t)(nok ? n : 0) * fstride;
+  AT acc_re[MT], acc_im[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    acc_re[t] = AT{0, 0, 0, 0};
+    acc_im[t] = AT{0, 0, 0, 0};
+  }
+  // each (spin, colour) row of 256 sites is summed in a fresh accumulator and
+  // then added to the total: accumulation depth 64 + 6 instead of 384
+#pragma unroll 1
+  for (int d = 0; d < 6; ++d) {
+    AT part_re[MT], part_im[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      part_re[t] = AT{0, 0, 0, 0};
+      part_im[t] = AT{0, 0, 0, 0};
+    }
+#pragma unroll 4
+    for (int l0 = 0; l0 < 256; l0 += 4) {
+      const int l = l0 + lk;
+      cpx<R> bv = ldcv<R>(vn, sidx(g, b, 6 * h + d, l));
+      if (!nok) bv = czero<R>();
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        const int i = 16 * t + ln;
+        cpx<R> p = i < ntv ? ldcv<R>(P, pidx(g, ntv, b, h, i, d, l)) : czero<R>();
+        // A = conj(P): (p.re, -p.im)
+        part_re[t] = tmfma(p.re, bv.re, part_re[t]);
+        part_re[t] = tmfma(p.im, bv.im, part_re[t]);
+        part_im[t] = tmfma(p.re, bv.im, part_im[t]);
+        part_im[t] = tmfma(-p.im, bv.re, part_im[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      acc_re[t] += part_re[t];
+      acc_im[t] += part_im[t];
+    }
+  }
+  if (!nok) return;
+  const int nc = 2 * ntv;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * t + trow<R>(lane, r);
+      if (i < ntv) stcv(y + ((int64_t)n * g.nb + b) * nc, h * ntv + i, cpx<R>{acc_re[t][r], acc_im[t][r]});
+    }
+}
+
 template <typename S>
 void restrict_t(const qmg_ctx* c, void* yc, const void* v, int nrhs, hipStream_t s, int p) {
   using P = typename PT<S>::stor;
   using R = typename PT<S>::real;
   const int bs = 1 << c->g.bs_log;
   size_t lds = sizeof(R) * 16 * std::max(bs, 4);
+  if (nrhs >= c->tune.restrict_mfma_min_rhs && bs == 256 && c->ntv <= 32) {
+    dim3 grid(c->g.nb, (nrhs + 15) / 16);
+    const int mt = (c->ntv + 15) / 16;
+    auto go = [&](auto mtc) {
+      constexpr int MT = decltype(mtc)::value;
+      if (p == QMG_F64)
+        hipLaunchKernelGGL((k_restrict_mfma<S, double, MT>), grid, dim3(128), 0, s, c->g, (double2*)yc,
+                           (const P*)c->P[p], (const P*)v, c->ntv, nrhs, (int64_t)field_elems(c));
+      else
+        hipLaunchKernelGGL((k_restrict_mfma<S, float, MT>), grid, dim3(128), 0, s, c->g, (float2*)yc,
+                           (const P*)c->P[p], (const P*)v, c->ntv, nrhs, (int64_t)field_elems(c));
+    };
+    if (mt == 1) go(std::integral_constant<int, 1>{});
+    else go(std::integral_constant<int, 2>{});
+    return;
+  }
   if (nrhs > 1 && c->tune.transfer_mr) {
     constexpr int RR = std::is_same<S, double>::value ? 2 : 4;
     const int ng = (nrhs + RR - 1) / RR;
