@@ -29,6 +29,23 @@ template <typename T> QMG_HD cpx<T> cmul_conj(cpx<T> a, cpx<T> b) {
   return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 template <typename T> QMG_HD T norm2(cpx<T> a) { return a.re * a.re + a.im * a.im; }
+// fused multiply-add chains (the compiler does not contract a + (b*c - d*e))
+QMG_HD float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+QMG_HD double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc += a * b
+template <typename T> QMG_HD void cfma(cpx<T>& acc, cpx<T> a, cpx<T> b) {
+  acc.re = fmar(a.re, b.re, acc.re);
+  acc.re = fmar(-a.im, b.im, acc.re);
+  acc.im = fmar(a.re, b.im, acc.im);
+  acc.im = fmar(a.im, b.re, acc.im);
+}
+// acc += conj(a) * b
+template <typename T> QMG_HD void cfma_conj(cpx<T>& acc, cpx<T> a, cpx<T> b) {
+  acc.re = fmar(a.re, b.re, acc.re);
+  acc.re = fmar(a.im, b.im, acc.re);
+  acc.im = fmar(a.re, b.im, acc.im);
+  acc.im = fmar(-a.im, b.re, acc.im);
+}
 template <typename T> QMG_HD cpx<T> czero() { return {T(0), T(0)}; }
 
 // ------------------------------------------------------------- precisions --
@@ -214,7 +231,12 @@ QMG_HD Half<R> umul(const Link<R>& U, const Half<R>& h) {
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      o.h[s][a] = U.u[a][0] * h.h[s][0] + U.u[a][1] * h.h[s][1] + U.u[a][2] * h.h[s][2];
+    {
+      cpx<R> t = U.u[a][0] * h.h[s][0];
+      cfma(t, U.u[a][1], h.h[s][1]);
+      cfma(t, U.u[a][2], h.h[s][2]);
+      o.h[s][a] = t;
+    }
   return o;
 }
 // w = U^H h
@@ -225,8 +247,12 @@ QMG_HD Half<R> udagmul(const Link<R>& U, const Half<R>& h) {
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      o.h[s][a] = cmul_conj(U.u[0][a], h.h[s][0]) + cmul_conj(U.u[1][a], h.h[s][1]) +
-                  cmul_conj(U.u[2][a], h.h[s][2]);
+    {
+      cpx<R> t = cmul_conj(U.u[0][a], h.h[s][0]);
+      cfma_conj(t, U.u[1][a], h.h[s][1]);
+      cfma_conj(t, U.u[2][a], h.h[s][2]);
+      o.h[s][a] = t;
+    }
   return o;
 }
 

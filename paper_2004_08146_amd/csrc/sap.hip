@@ -297,19 +297,22 @@ __device__ __forceinline__ void res_hop44(Spinor<float>& acc, const P* x, const 
   }
 }
 
-// block-restricted hop: neighbour from LDS rho, link from LDS, dropped outside
+// block-restricted hop: neighbour from LDS rho, link from LDS.  Branch free: a
+// lane whose neighbour lies outside the block reads the zero pad (sites
+// 256..319 of each component row, stride kRhStride) and so adds nothing.
+constexpr int kRhStride = 320;
 template <int HOP>
 __device__ __forceinline__ void blk_hop44(Spinor<float>& acc, const cpx<float>* rh, const cpx<float>* Ul, uint32_t l) {
   constexpr int MU = HOP / 2;
   constexpr bool FWD = HOP % 2 == 0;
   constexpr int SH = kSh44[MU];
   const uint32_t lc = (l >> SH) & 3u;
-  if (FWD ? lc < 3u : lc > 0u) {
-    const uint32_t ln = FWD ? l + (1u << SH) : l - (1u << SH);
-    const Half<float> h = project(lds_spinor(rh, (int)ln, 256), MU, FWD);
-    const Link<float> u = lds_link(Ul, MU, FWD ? l : ln);
-    accum_recon(acc, FWD ? umul(u, h) : udagmul(u, h), MU, FWD);
-  }
+  const bool in = FWD ? lc < 3u : lc > 0u;
+  const uint32_t ln = FWD ? l + (1u << SH) : l - (1u << SH);
+  const uint32_t ls = in ? ln : 256u + (l & 63u);
+  const Half<float> h = project(lds_spinor(rh, (int)ls, kRhStride), MU, FWD);
+  const Link<float> u = lds_link(Ul, MU, (FWD || !in) ? l : ln);
+  accum_recon(acc, FWD ? umul(u, h) : udagmul(u, h), MU, FWD);
 }
 
 // (m0+4 + C) v - tau Gamma5 v with the clover blocks held in registers
@@ -333,8 +336,8 @@ __device__ __forceinline__ Spinor<float> diag_reg(const cpx<float> (&dg)[2][18],
       for (int i = 1; i < 6; ++i)
 #pragma unroll
         for (int j = 0; j < i; ++j) {
-          w[i] = w[i] + dg[h][k] * in[j];
-          w[j] = w[j] + cmul_conj(dg[h][k], in[i]);
+          cfma(w[i], dg[h][k], in[j]);
+          cfma_conj(w[j], dg[h][k], in[i]);
           ++k;
         }
 #pragma unroll
@@ -378,7 +381,7 @@ template <typename S, bool CLOVER, int NS>
 __global__ __launch_bounds__(256 * NS) void k_sap44(SapArgs<S> a) {
   using P = typename PT<S>::stor;
   __shared__ cpx<float> Ul[36 * 256];
-  __shared__ cpx<float> rhs_lds[NS][12 * 256];
+  __shared__ cpx<float> rhs_lds[NS][12 * kRhStride];
   __shared__ float red[2][4 * NS * 3];
   int rb = 0;
   const int w = blockIdx.x, nw = gridDim.x;
@@ -388,6 +391,7 @@ __global__ __launch_bounds__(256 * NS) void k_sap44(SapArgs<S> a) {
   const int slot = (int)(threadIdx.x >> 8);
   cpx<float>* rh = rhs_lds[slot];
   const int* nbr = a.g.nbr;
+  for (int i = (int)l; i < 12 * 64; i += 256) rh[(i >> 6) * kRhStride + 256 + (i & 63)] = czero<float>();
   for (int i = slot; i < 36; i += NS) {
     auto v = cv(ldo(a.U, ((b * 36u + (uint32_t)i) << 8) + l));
     Ul[i * 256 + l] = cpx<float>{float(v.re), float(v.im)};
@@ -446,7 +450,7 @@ __global__ __launch_bounds__(256 * NS) void k_sap44(SapArgs<S> a) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rh[(3 * s + c) * 256 + l] = rho.s[s][c];
+        for (int c = 0; c < 3; ++c) rh[(3 * s + c) * kRhStride + l] = rho.s[s][c];
       __syncthreads();
 #pragma unroll
       for (int s = 0; s < 4; ++s)
