@@ -108,8 +108,8 @@ __global__ __launch_bounds__(256) void k_dot_stage2(double* dots, const double* 
   }
 }
 
-template <typename S>
-__global__ __launch_bounds__(256) void k_multiaxpy(typename PT<S>::stor* w, const typename PT<S>::stor* V,
+template <typename S, typename SV = S>
+__global__ __launch_bounds__(256) void k_multiaxpy(typename PT<S>::stor* w, const typename PT<SV>::stor* V,
                                                    int64_t vstride, int J, const double* coef, int64_t n,
                                                    int64_t stride) {
   using R = typename PT<S>::real;
@@ -219,6 +219,17 @@ hipError_t launch_multiaxpy(int p, void* w, const void* V, int64_t vstride, int 
     using P = typename PT<S>::stor;
     hipLaunchKernelGGL(k_multiaxpy<S>, dim3(ew_grid(n), nrhs), dim3(256), 0, s, (P*)w, (const P*)V, vstride, J,
                        coef, n, stride);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_multiaxpy_d(void* w, const void* V, int vprec, int64_t vstride, int J, const double* coef,
+                              int64_t n, int64_t stride, int nrhs, hipStream_t s) {
+  by_prec(vprec, [&](auto tag) {
+    using SV = decltype(tag);
+    using PV = typename PT<SV>::stor;
+    hipLaunchKernelGGL((k_multiaxpy<double, SV>), dim3(ew_grid(n), nrhs), dim3(256), 0, s, (double2*)w, (const PV*)V,
+                       vstride, J, coef, n, stride);
   });
   return hipGetLastError();
 }

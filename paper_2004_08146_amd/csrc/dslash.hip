@@ -12,10 +12,13 @@
 
 namespace {
 
-template <typename S>
+// SI: storage type of the input field (the output, links and clover use S); an
+// FP64 apply may read a field stored in FP32 or BF16 with no change in its
+// arithmetic, since every such value is exact in FP64.
+template <typename S, typename SI = S>
 struct DsArgs {
   typename PT<S>::stor* out;
-  const typename PT<S>::stor* in;
+  const typename PT<SI>::stor* in;
   const typename PT<S>::stor* U;
   const typename PT<S>::stor* diag;
   double mass4;
@@ -27,8 +30,8 @@ struct DsArgs {
 };
 
 // acc += (I - g_mu) U_mu(x) psi(x+mu) + (I + g_mu) U_mu(x-mu)^H psi(x-mu)
-template <typename R, int MU, typename P>
-__device__ __forceinline__ void hop_pair(Spinor<R>& acc, const P* in, const P* U, const Geom& g, int b, int l) {
+template <typename R, int MU, typename PI, typename P>
+__device__ __forceinline__ void hop_pair(Spinor<R>& acc, const PI* in, const P* U, const Geom& g, int b, int l) {
   int bn, ln;
   nb_fwd(g, b, l, MU, bn, ln);
   {
@@ -42,8 +45,8 @@ __device__ __forceinline__ void hop_pair(Spinor<R>& acc, const P* in, const P* U
   }
 }
 
-template <typename S, bool CLOVER, int MODE, bool UB>
-__global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a) {
+template <typename S, bool CLOVER, int MODE, bool UB, typename SI>
+__global__ __launch_bounds__(256) void k_dslash(DsArgs<S, SI> a) {
   using R = typename PT<S>::real;
   const Geom& g = a.g;
   const int w = blockIdx.x, nw = gridDim.x;
@@ -131,8 +134,8 @@ __device__ __forceinline__ Link<C> ld_link44(const P* U, uint32_t b, int mu, uin
 }
 
 // one hop (HOP = 2 mu for x + mu, 2 mu + 1 for x - mu) for R right-hand sides
-template <typename C, int HOP, int R, typename P>
-__device__ __forceinline__ void hop44(Spinor<C> (&acc)[R], const P* const (&in)[R], const P* U, const int* nbr,
+template <typename C, int HOP, int R, typename PI, typename P>
+__device__ __forceinline__ void hop44(Spinor<C> (&acc)[R], const PI* const (&in)[R], const P* U, const int* nbr,
                                       uint32_t b, uint32_t l, int nr) {
   constexpr int MU = HOP / 2;
   constexpr bool FWD = (HOP % 2) == 0;
@@ -158,8 +161,8 @@ __device__ __forceinline__ void hop44(Spinor<C> (&acc)[R], const P* const (&in)[
   }
 }
 
-template <typename S, bool CLOVER, int MODE, int R, int W, bool LOOP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1))) void k_dslash44(DsArgs<S> a) {
+template <typename S, bool CLOVER, int MODE, int R, int W, bool LOOP, typename SI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1))) void k_dslash44(DsArgs<S, SI> a) {
   using C = typename PT<S>::real;
   using P = typename PT<S>::stor;
   const int w = blockIdx.x, nw = gridDim.x;
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W > 0 ? W :
   for (int kg = LOOP ? 0 : L % ng; kg < (LOOP ? ng : L % ng + 1); ++kg) {
   const int k0 = kg * R;
   const int nr = a.nrhs - k0 < R ? a.nrhs - k0 : R;
-  const P* in[R];
+  const typename PT<SI>::stor* in[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) in[r] = a.in + (size_t)(k0 + (r < nr ? r : 0)) * a.fstride;
   Spinor<C> acc[R];
@@ -226,19 +229,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W > 0 ? W :
   }
 }
 
-template <typename S, bool CLOVER, int MODE, int R, int W, bool LOOP = false>
-void launch44(const DsArgs<S>& a, int nb, hipStream_t s) {
+template <typename S, bool CLOVER, int MODE, int R, int W, bool LOOP = false, typename SI>
+void launch44(const DsArgs<S, SI>& a, int nb, hipStream_t s) {
   const unsigned ng = LOOP ? 1u : (unsigned)((a.nrhs + R - 1) / R);
-  hipLaunchKernelGGL((k_dslash44<S, CLOVER, MODE, R, W, LOOP>), dim3((unsigned)nb * ng), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_dslash44<S, CLOVER, MODE, R, W, LOOP, SI>), dim3((unsigned)nb * ng), dim3(256), 0, s, a);
 }
 
-template <typename S, bool CLOVER, int MODE>
+template <typename S, bool CLOVER, int MODE, typename SI = S>
 void launch_t(const qmg_ctx* c, void* out, const void* in, const double* tau, int nrhs, hipStream_t s,
               int p) {
   using P = typename PT<S>::stor;
-  DsArgs<S> a;
+  DsArgs<S, SI> a;
   a.out = (P*)out;
-  a.in = (const P*)in;
+  a.in = (const typename PT<SI>::stor*)in;
   a.U = (const P*)c->U[p];
   a.diag = (const P*)c->Dg[p];
   a.mass4 = c->m0 + 4.0;
@@ -267,9 +270,9 @@ void launch_t(const qmg_ctx* c, void* out, const void* in, const double* tau, in
   const int wg = 256;
   unsigned nwg = (unsigned)((c->g.V + wg - 1) / wg) * (unsigned)nrhs;
   if ((1 << c->g.bs_log) >= wg)
-    hipLaunchKernelGGL((k_dslash<S, CLOVER, MODE, true>), dim3(nwg), dim3(wg), 0, s, a);
+    hipLaunchKernelGGL((k_dslash<S, CLOVER, MODE, true, SI>), dim3(nwg), dim3(wg), 0, s, a);
   else
-    hipLaunchKernelGGL((k_dslash<S, CLOVER, MODE, false>), dim3(nwg), dim3(wg), 0, s, a);
+    hipLaunchKernelGGL((k_dslash<S, CLOVER, MODE, false, SI>), dim3(nwg), dim3(wg), 0, s, a);
 }
 
 template <typename S>
@@ -291,5 +294,18 @@ hipError_t launch_dslash(const qmg_ctx* c, int p, void* out, const void* in, con
   if (p == QMG_F64) launch_p<double>(c, out, in, tau, nrhs, mode, s, p);
   else if (p == QMG_F32) launch_p<float>(c, out, in, tau, nrhs, mode, s, p);
   else launch_p<bf16_t>(c, out, in, tau, nrhs, mode, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_dslash_d_in(const qmg_ctx* c, void* out, const void* in, int in_prec, const double* tau,
+                              int nrhs, hipStream_t s) {
+  if (in_prec == QMG_F64) return launch_dslash(c, QMG_F64, out, in, tau, nrhs, 0, s);
+  if (c->clover) {
+    if (in_prec == QMG_F32) launch_t<double, true, 0, float>(c, out, in, tau, nrhs, s, QMG_F64);
+    else launch_t<double, true, 0, bf16_t>(c, out, in, tau, nrhs, s, QMG_F64);
+  } else {
+    if (in_prec == QMG_F32) launch_t<double, false, 0, float>(c, out, in, tau, nrhs, s, QMG_F64);
+    else launch_t<double, false, 0, bf16_t>(c, out, in, tau, nrhs, s, QMG_F64);
+  }
   return hipGetLastError();
 }

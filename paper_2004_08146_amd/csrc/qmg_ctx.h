@@ -86,6 +86,9 @@ hipError_t launch_clover(const Geom& g, void* diag64, const void* U64, double m0
 // ---- dslash.hip   mode 0: (D - tau Gamma5), mode 1: (Gamma5 D - tau)
 hipError_t launch_dslash(const qmg_ctx* c, int p, void* out, const void* in, const double* tau,
                          int nrhs, int mode, hipStream_t s);
+// (D - tau Gamma5) in FP64 arithmetic and storage, reading an input field stored in in_prec
+hipError_t launch_dslash_d_in(const qmg_ctx* c, void* out, const void* in, int in_prec, const double* tau,
+                              int nrhs, hipStream_t s);
 // ---- sap.hip
 hipError_t launch_sap_colour(const qmg_ctx* c, int p, void* x, const void* f, const double* tau,
                              int nrhs, int colour, int n_mr, hipStream_t s);
@@ -110,6 +113,9 @@ hipError_t launch_axpy_norm(int p, void* w, const void* V, int64_t vstride, int 
 // w_k += sum_j coef[k*J + j] * V_j,k   (coef complex double on device)
 hipError_t launch_multiaxpy(int p, void* w, const void* V, int64_t vstride, int J, const double* coef,
                             int64_t n, int64_t stride, int nrhs, hipStream_t s);
+// as launch_multiaxpy with w in FP64 and the J vectors V stored in vprec
+hipError_t launch_multiaxpy_d(void* w, const void* V, int vprec, int64_t vstride, int J, const double* coef,
+                              int64_t n, int64_t stride, int nrhs, hipStream_t s);
 // y_k = a_k * x_k (a complex double on device, may alias)
 hipError_t launch_scale(int p, void* y, const void* x, const double* a, int64_t n, int64_t stride,
                         int nrhs, hipStream_t s);
@@ -128,8 +134,9 @@ qmg_status solver_coarse_gmres(qmg_ctx* c, int p, void* y, const void* r, const 
                                int iters, double tol, int* iters_done, hipStream_t s);
 qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
                                hipStream_t s);
+// z = M r; z is written in precision zprec (FP64, or the preconditioner's own precision)
 qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs,
-                         const qmg_params* prm, int* coarse_iters, hipStream_t s);
+                         const qmg_params* prm, int* coarse_iters, hipStream_t s, int zprec = QMG_F64);
 qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, int nrhs,
                          const qmg_params* prm, qmg_stats* st, hipStream_t s);
 qmg_status build_mg(qmg_ctx* c, const void* W, int ntv, hipStream_t s);

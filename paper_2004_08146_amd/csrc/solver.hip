@@ -121,13 +121,15 @@ struct Space {
     return QMG_OK;
   }
   // w_k += sum_j coef[k*J + j] V_j,k
-  qmg_status axpy(void* w, const void* V, int J, int64_t vstr, const std::vector<cd>& coef) {
+  qmg_status axpy(void* w, const void* V, int J, int64_t vstr, const std::vector<cd>& coef, int vprec = -1) {
     double* d = (double*)ws_get(c, "sp_coef", sizeof(double) * 2 * J * nrhs);
     if (!d) return set_err(c, QMG_E_NOMEM, "out of device memory (coef)");
     double* h = host_buf(c, "coef", 2 * J * nrhs);
     for (int i = 0; i < J * nrhs; ++i) { h[2 * i] = coef[i].real(); h[2 * i + 1] = coef[i].imag(); }
     hipError_t e = hipMemcpyAsync(d, h, sizeof(double) * 2 * J * nrhs, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_multiaxpy(p, w, V, vstr, J, d, n, n, nrhs, s);
+    if (e == hipSuccess)
+      e = (vprec < 0 || vprec == p) ? launch_multiaxpy(p, w, V, vstr, J, d, n, n, nrhs, s)
+                                    : launch_multiaxpy_d(w, V, vprec, vstr, J, d, n, n, nrhs, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host coef buffer is reused next call
     if (e != hipSuccess) return hip_err(c, e, "axpy");
     return QMG_OK;
@@ -264,17 +266,18 @@ qmg_status solver_coarse_gmres(qmg_ctx* c, int p, void* y, const void* r, const 
 // graph_safe: the coarse GMRES runs a fixed number of steps with its scalars on
 // the device, so the whole V-cycle is a pure kernel sequence (no host sync).
 static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
-                              int* coarse_iters, hipStream_t s, bool graph_safe);
+                              int* coarse_iters, hipStream_t s, bool graph_safe, int zprec);
 
 qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
-                         int* coarse_iters, hipStream_t s) {
-  if (!prm->use_graph) return vcycle_body(c, z, r, tau, nrhs, prm, coarse_iters, s, false);
+                         int* coarse_iters, hipStream_t s, int zprec) {
+  if (zprec != QMG_F64 && zprec != prm->mg_prec) return set_err(c, QMG_E_ARG, "V-cycle output precision");
+  if (!prm->use_graph) return vcycle_body(c, z, r, tau, nrhs, prm, coarse_iters, s, false, zprec);
   // HIP-graph mode: capture the V-cycle once per (buffers, shifts, parameters) and replay it
   std::string key;
   {
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%p|%p|%d|%d|%d|%d|%d|%d|", z, r, nrhs, prm->nu_post, prm->n_mr,
-                  prm->coarse_maxiter, (int)prm->mg_prec, prm->use_coarse);
+    std::snprintf(buf, sizeof(buf), "%p|%p|%d|%d|%d|%d|%d|%d|%d|", z, r, nrhs, prm->nu_post, prm->n_mr,
+                  prm->coarse_maxiter, (int)prm->mg_prec, prm->use_coarse, zprec);
     key = buf;
     for (int k = 0; k < nrhs; ++k) {
       std::snprintf(buf, sizeof(buf), "%.17g,", tau[k]);
@@ -291,7 +294,7 @@ qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, 
   // workspace buffer), then record the same sequence on the library's own
   // stream (the caller's stream may be the legacy default stream, which
   // cannot be captured); the recorded graph is later launched on `s`.
-  qmg_status st = vcycle_body(c, z, r, tau, nrhs, prm, nullptr, s, true);
+  qmg_status st = vcycle_body(c, z, r, tau, nrhs, prm, nullptr, s, true, zprec);
   if (st != QMG_OK) return st;
   hipError_t e = hipSuccess;
   if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
@@ -301,7 +304,7 @@ qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, 
   hipGraph_t graph = nullptr;
   e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_err(c, e, "begin capture");
-  st = vcycle_body(c, z, r, tau, nrhs, prm, nullptr, c->cap_stream, true);
+  st = vcycle_body(c, z, r, tau, nrhs, prm, nullptr, c->cap_stream, true, zprec);
   e = hipStreamEndCapture(c->cap_stream, &graph);
   if (st != QMG_OK) {
     if (graph) hipGraphDestroy(graph);
@@ -321,7 +324,7 @@ qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, 
 }
 
 static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
-                              int* coarse_iters, hipStream_t s, bool graph_safe) {
+                              int* coarse_iters, hipStream_t s, bool graph_safe, int zprec) {
   const int p = prm->mg_prec;
   const int64_t n = (int64_t)field_elems(c);
   void* rp = (void*)r;
@@ -329,7 +332,8 @@ static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* 
   hipError_t e;
   if (p != QMG_F64) {
     rp = ws_get(c, "vc_r", (size_t)n * nrhs * cbytes(p));
-    zp = ws_get(c, "vc_z", (size_t)n * nrhs * cbytes(p));
+    // with zprec == p the result is written straight into z
+    if (zprec != p) zp = ws_get(c, "vc_z", (size_t)n * nrhs * cbytes(p));
     if (!rp || !zp) return set_err(c, QMG_E_NOMEM, "out of device memory (V-cycle)");
     e = launch_convert(rp, p, r, QMG_F64, n * nrhs, s);
     if (e != hipSuccess) return hip_err(c, e, "convert");
@@ -360,7 +364,7 @@ static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* 
       e = launch_sap_colour(c, p, zp, rp, tau, nrhs, col, prm->n_mr, s);
       if (e != hipSuccess) return hip_err(c, e, "sap");
     }
-  if (p != QMG_F64) {
+  if (p != QMG_F64 && zprec != p) {
     e = launch_convert(z, QMG_F64, zp, p, n * nrhs, s);
     if (e != hipSuccess) return hip_err(c, e, "convert");
   }
@@ -374,8 +378,14 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
   const int m = std::max(1, prm->restart);
   Space sp{c, QMG_F64, (int64_t)field_elems(c), nrhs, s};
   const size_t bb = sp.bbytes();
+  // the preconditioned directions Z are kept in the preconditioner's own
+  // precision: the V-cycle output is exact there, so the FP64 products read it
+  // unchanged and half (or a quarter) of the bytes
+  const int zprec = prm->mg_prec;
+  const size_t zb = (size_t)sp.n * nrhs * cbytes(zprec);
   void* V = ws_get(c, "fg_V", bb * (m + 1));
-  void* Z = ws_get(c, "fg_Z", bb * m);
+  void* Z = ws_get(c, "fg_Z", zb * m);
+  auto zat = [&](int j) { return (void*)((char*)Z + (size_t)j * zb); };
   void* f = ws_get(c, "fg_f", bb);
   void* r = ws_get(c, "fg_r", bb);
   void* w = ws_get(c, "fg_w", bb);
@@ -416,9 +426,9 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
     std::vector<int> kk(nrhs, 0);
     for (int j = 0; j < m; ++j) {
       int ci = 0;
-      st = solver_vcycle(c, sp.at(Z, j), sp.at(V, j), tau, nrhs, prm, &ci, s);
+      st = solver_vcycle(c, zat(j), sp.at(V, j), tau, nrhs, prm, &ci, s, zprec);
       if (st != QMG_OK) return st;
-      e = launch_dslash(c, QMG_F64, w, sp.at(Z, j), tau, nrhs, 0, s);
+      e = launch_dslash_d_in(c, w, zat(j), zprec, tau, nrhs, s);
       if (e != hipSuccess) return hip_err(c, e, "apply");
       std::vector<std::vector<cd>> h;
       st = sp.arnoldi(h, V, j, w);
@@ -453,7 +463,7 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
           coef[(size_t)k * J + i] = yk[i];
         }
       }
-      st = sp.axpy(x, Z, J, sp.vstride(), coef);
+      st = sp.axpy(x, Z, J, sp.vstride(), coef, zprec);
       if (st != QMG_OK) return st;
     }
     // true residual r = Gamma5 b - A_tau x
