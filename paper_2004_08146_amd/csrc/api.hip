@@ -1,5 +1,6 @@
 // The C interface: context, validation, error reporting and dispatch to the
 // kernel launchers and solver drivers.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -106,6 +107,47 @@ void free_ptr(void*& p) {
 
 }  // namespace
 
+qmg_status set_ds_order(qmg_ctx* c, int order) {
+  if (order < 0 || order >= kNumDsOrders) return set_err(c, QMG_E_ARG, "stencil order");
+  const Geom& g = c->g;
+  int T[4];
+  for (int mu = 0; mu < 4; ++mu) {
+    T[mu] = std::min(kTileShapes[order][mu], g.nbk[mu]);
+    while (g.nbk[mu] % T[mu] != 0) --T[mu];
+  }
+  std::vector<int> id_of_lex((size_t)g.nb);
+  for (int b = 0; b < g.nb; ++b) id_of_lex[(size_t)c->lex_of_block[b]] = b;
+  std::vector<int> tord;
+  tord.reserve((size_t)g.nb);
+  int nt[4];
+  for (int mu = 0; mu < 4; ++mu) nt[mu] = g.nbk[mu] / T[mu];
+  for (int t0 = 0; t0 < nt[0]; ++t0)
+    for (int t1 = 0; t1 < nt[1]; ++t1)
+      for (int t2 = 0; t2 < nt[2]; ++t2)
+        for (int t3 = 0; t3 < nt[3]; ++t3)
+          for (int i0 = 0; i0 < T[0]; ++i0)
+            for (int i1 = 0; i1 < T[1]; ++i1)
+              for (int i2 = 0; i2 < T[2]; ++i2)
+                for (int i3 = 0; i3 < T[3]; ++i3) {
+                  const int X[4] = {t0 * T[0] + i0, t1 * T[1] + i1, t2 * T[2] + i2, t3 * T[3] + i3};
+                  const int lex = ((X[0] * g.nbk[1] + X[1]) * g.nbk[2] + X[2]) * g.nbk[3] + X[3];
+                  tord.push_back(id_of_lex[(size_t)lex]);
+                }
+  std::vector<char> seen((size_t)g.nb, 0);
+  for (int b : tord) {
+    if (b < 0 || b >= g.nb || seen[(size_t)b]) return set_err(c, QMG_E_STATE, "stencil order is not a permutation");
+    seen[(size_t)b] = 1;
+  }
+  if ((int)tord.size() != g.nb) return set_err(c, QMG_E_STATE, "stencil order is not a permutation");
+  if (!c->d_tord && hipMalloc(&c->d_tord, sizeof(int) * (size_t)g.nb) != hipSuccess)
+    return set_err(c, QMG_E_NOMEM, "stencil order table");
+  hipError_t e = hipMemcpy(c->d_tord, tord.data(), sizeof(int) * (size_t)g.nb, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_err(c, e, "stencil order table");
+  c->tile_blocks = T[0] * T[1] * T[2] * T[3];
+  c->tune.ds_order = order;
+  return QMG_OK;
+}
+
 extern "C" {
 
 qmg_params qmg_default_params(void) {
@@ -199,9 +241,14 @@ qmg_status qmg_create(qmg_ctx** out, const int dims[4], const int block[4], int 
   g.nbr = c->d_nbr;
   g.bcoord = c->d_bcoord;
   g.lexord = c->d_lexord;
+  if (set_ds_order(c, c->tune.ds_order) != QMG_OK) {
+    qmg_destroy(c);
+    return QMG_E_HIP;
+  }
   *out = c;
   return QMG_OK;
 }
+
 
 qmg_status qmg_destroy(qmg_ctx* c) {
   if (!c) return QMG_OK;
@@ -217,6 +264,7 @@ qmg_status qmg_destroy(qmg_ctx* c) {
   if (c->d_nbr) hipFree(c->d_nbr);
   if (c->d_bcoord) hipFree(c->d_bcoord);
   if (c->d_lexord) hipFree(c->d_lexord);
+  if (c->d_tord) hipFree(c->d_tord);
   delete c;
   return QMG_OK;
 }

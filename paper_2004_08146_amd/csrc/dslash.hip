@@ -25,6 +25,8 @@ struct DsArgs {
   int64_t fstride;  // complex elements per field
   int nrhs;
   int remap;
+  const int* tord;  // block ids in work order: tiles of tb blocks, each tile's rhs groups back to back
+  int tb;
   Geom g;
   double tau[QMG_MAXRHS];
 };
@@ -172,10 +174,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W > 0 ? W :
   // close together in time (and, with the XCD remap, on the same XCD).  With
   // LOOP one work-group walks all rhs groups of its block, so the block's
   // links are fetched from HBM once and re-read from cache.
-  const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane(a.g.lexord[LOOP ? L : L / ng]);
+  // Without LOOP, work-group L takes rhs group kg of one block, in tiles of tb
+  // blocks whose rhs groups run back to back (tb = 1: one block at a time).
+  uint32_t b;
+  int kbeg, kend;
+  if (LOOP) {
+    b = (uint32_t)__builtin_amdgcn_readfirstlane(a.g.lexord[L]);
+    kbeg = 0;
+    kend = ng;
+  } else {
+    const int per = a.tb * ng, ti = L / per, rem = L - ti * per;
+    kbeg = rem / a.tb;
+    kend = kbeg + 1;
+    b = (uint32_t)__builtin_amdgcn_readfirstlane(a.tord[ti * a.tb + (rem - kbeg * a.tb)]);
+  }
   const uint32_t l = threadIdx.x;
 #pragma unroll 1
-  for (int kg = LOOP ? 0 : L % ng; kg < (LOOP ? ng : L % ng + 1); ++kg) {
+  for (int kg = kbeg; kg < kend; ++kg) {
   const int k0 = kg * R;
   const int nr = a.nrhs - k0 < R ? a.nrhs - k0 : R;
   const typename PT<SI>::stor* in[R];
@@ -248,6 +263,8 @@ void launch_t(const qmg_ctx* c, void* out, const void* in, const double* tau, in
   a.fstride = (int64_t)field_elems(c);
   a.nrhs = nrhs;
   a.remap = c->tune.dslash_xcd_remap;
+  a.tord = c->d_tord;
+  a.tb = c->tile_blocks;
   a.g = c->g;
   for (int i = 0; i < QMG_MAXRHS; ++i) a.tau[i] = i < nrhs ? tau[i] : 0.0;
   const bool b44 = c->g.block[0] == 4 && c->g.block[1] == 4 && c->g.block[2] == 4 && c->g.block[3] == 4;

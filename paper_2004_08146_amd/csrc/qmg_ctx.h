@@ -23,6 +23,10 @@ struct DsVariant { int R, W; };
 constexpr DsVariant kDsVariants[] = {{0, 0}, {1, 0}, {1, 2}, {1, 3}, {1, 4}, {2, 0}, {2, 2}, {4, 0},
                                      {1, 2}, {2, 0}, {2, 2}};
 constexpr int kNumDsVariants = 11;
+// tiles of blocks (extent per direction, clamped to a divisor of the block grid)
+constexpr int kTileShapes[][4] = {{1, 1, 1, 1}, {2, 2, 2, 2}, {2, 2, 2, 4}, {2, 2, 4, 4},
+                                  {1, 2, 4, 8}, {2, 2, 4, 8}, {1, 1, 2, 8}, {1, 2, 2, 4}};
+constexpr int kNumDsOrders = 8;
 
 struct Tune {
   int dslash[3][2] = {{1, 1}, {1, 1}, {1, 1}};  // [prec][nrhs == 1 ? 0 : 1] -> variant index
@@ -33,6 +37,8 @@ struct Tune {
   int coarse_mfma = 1;                           // MFMA coarse apply for many right-hand sides
   int transfer_mr = 1;                           // restrict / prolong kernels sharing P loads across rhs
   int restrict_mfma_min_rhs = 4;                 // restriction on MFMA from this many rhs (1000: never)
+  int ds_order = 0;  // stencil work order: 0 blocks in lexicographic order, each with its rhs groups back to
+                     // back; t > 0 tiles of kTileShapes[t] blocks, each tile's rhs groups back to back
   int coarse_mfma_min_rhs = 4;                   // smallest batch that takes the MFMA path
   bool tuned = false;
 };
@@ -43,6 +49,8 @@ struct qmg_ctx {
   int* d_nbr = nullptr;
   int* d_bcoord = nullptr;
   int* d_lexord = nullptr;
+  int* d_tord = nullptr;       // block ids in stencil work order (tiles of tile_blocks blocks)
+  int tile_blocks = 1;
   std::vector<int> h_nbr, h_bcoord;
   std::vector<int64_t> lex_of_block;
   bool sap_ok = false;
@@ -69,6 +77,9 @@ struct qmg_ctx {
 
 size_t field_elems(const qmg_ctx* c);   // complex elements in one fine field
 size_t coarse_elems(const qmg_ctx* c);  // complex elements in one coarse vector
+
+// stencil work order (tile shape index into kTileShapes); synchronous, not for use under capture
+qmg_status set_ds_order(qmg_ctx* c, int order);
 
 // named, lazily grown device workspace (never shrinks; freed by qmg_destroy)
 void* ws_get(qmg_ctx* c, const std::string& name, size_t bytes);

@@ -151,7 +151,10 @@ struct Space {
   // One pass leaves an orthogonality error of about eps ||w|| / ||w_new||
   // (<= 20 eps here); the true residual is recomputed after every restart
   // cycle anyway.  The new norm comes out of the update pass.
-  qmg_status arnoldi(std::vector<std::vector<cd>>& h, void* V, int j, void* w) {
+  // sig (optional, [nrhs][j + 1]): the basis is stored unnormalised, v_i = sig_i W_i,
+  // so the projections use sig_i (W_i^H w) and the update subtracts sig_i^2 (W_i^H w) W_i
+  qmg_status arnoldi(std::vector<std::vector<cd>>& h, void* V, int j, void* w,
+                     const std::vector<std::vector<double>>* sig = nullptr) {
     const int J = j + 1;
     h.assign(nrhs, std::vector<cd>(j + 2, cd(0)));
     double* d = (double*)ws_get(c, "sp_dots", sizeof(double) * 2 * (J + 1) * nrhs);
@@ -170,9 +173,10 @@ struct Space {
       for (int k = 0; k < nrhs; ++k) {
         for (int i = 0; i < J; ++i) {
           const double* q = hd + 2 * ((size_t)k * (J + self) + i);
-          h[k][i] += cd(q[0], q[1]);
-          hc[2 * ((size_t)k * J + i)] = -q[0];
-          hc[2 * ((size_t)k * J + i) + 1] = -q[1];
+          const double si = sig ? (*sig)[k][i] : 1.0;
+          h[k][i] += si * cd(q[0], q[1]);
+          hc[2 * ((size_t)k * J + i)] = -si * si * q[0];
+          hc[2 * ((size_t)k * J + i) + 1] = -si * si * q[1];
         }
         if (self) before[k] = hd[2 * ((size_t)k * (J + 1) + J)];
       }
@@ -388,8 +392,7 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
   auto zat = [&](int j) { return (void*)((char*)Z + (size_t)j * zb); };
   void* f = ws_get(c, "fg_f", bb);
   void* r = ws_get(c, "fg_r", bb);
-  void* w = ws_get(c, "fg_w", bb);
-  if (!V || !Z || !f || !r || !w) return set_err(c, QMG_E_NOMEM, "out of device memory (FGMRES)");
+  if (!V || !Z || !f || !r) return set_err(c, QMG_E_NOMEM, "out of device memory (FGMRES)");
   hipError_t e = launch_gamma5_bs(QMG_F64, f, b, sp.n * nrhs, c->g.bs_log, s);
   if (e == hipSuccess) e = launch_fill_zero(x, bb, s);
   if (e == hipSuccess) e = hipMemcpyAsync(r, f, bb, hipMemcpyDeviceToDevice, s);
@@ -423,15 +426,21 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
     }
     st = sp.scale(sp.at(V, 0), r, a);
     if (st != QMG_OK) return st;
+    // basis vectors after the first stay unnormalised (v_j = sig_j W_j): the
+    // product A z_j is orthogonalised in place in the next basis slot, and the
+    // preconditioner takes W_j itself (flexible GMRES allows any z_j)
+    std::vector<std::vector<double>> sig(nrhs, std::vector<double>(m + 1, 0.0));
+    for (int k = 0; k < nrhs; ++k) sig[k][0] = 1.0;
     std::vector<int> kk(nrhs, 0);
     for (int j = 0; j < m; ++j) {
       int ci = 0;
+      void* w = sp.at(V, j + 1);
       st = solver_vcycle(c, zat(j), sp.at(V, j), tau, nrhs, prm, &ci, s, zprec);
       if (st != QMG_OK) return st;
       e = launch_dslash_d_in(c, w, zat(j), zprec, tau, nrhs, s);
       if (e != hipSuccess) return hip_err(c, e, "apply");
       std::vector<std::vector<cd>> h;
-      st = sp.arnoldi(h, V, j, w);
+      st = sp.arnoldi(h, V, j, w, &sig);
       if (st != QMG_OK) return st;
       bool all = true;
       for (int k = 0; k < nrhs; ++k) {
@@ -442,13 +451,16 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
         cits[k] += ci;
         const double hn = h[k][j + 1].real();
         if (hn == 0.0 || est <= prm->tol * bnorm[k]) act[k] = 0;
-        a[k] = act[k] ? 1.0 / hn : 0.0;
         all = all && !act[k];
+      }
+      // converged right-hand sides are orthogonalised like the others, so their
+      // vectors stay bounded; their coefficients are no longer used
+      for (int k = 0; k < nrhs; ++k) {
+        const double hn = h[k][j + 1].real();
+        sig[k][j + 1] = (hn > 0.0 && std::isfinite(hn)) ? 1.0 / hn : 0.0;
       }
       ++total;
       if (all || j + 1 == m || total >= prm->maxiter) break;
-      st = sp.scale(sp.at(V, j + 1), w, a);
-      if (st != QMG_OK) return st;
     }
     int J = 0;
     for (int k = 0; k < nrhs; ++k) J = std::max(J, kk[k]);

@@ -62,6 +62,14 @@ bool load_cache(qmg_ctx* c, const std::string& path, const std::string& key) {
       c->tune.dslash_xcd_remap = vr;
   }
   {
+    const std::string ko = "\"" + key + "|ds_order\":";
+    const size_t po = txt.find(ko);
+    int vo = -1;
+    if (po != std::string::npos && std::sscanf(txt.c_str() + po + ko.size(), " %d", &vo) == 1 && vo >= 0 &&
+        vo < kNumDsOrders)
+      set_ds_order(c, vo);
+  }
+  {
     const std::string kc = "\"" + key + "|coarse_mfma\":";
     const size_t pc = txt.find(kc);
     int vc = -1;

@@ -130,6 +130,29 @@ def _force_variant(lat, tmp_path, dims, block, clover, v):
     lat.autotune(str(path))
 
 
+@pytest.mark.parametrize("order,variant", [(1, 1), (4, 1), (6, 5), (7, 2)])
+def test_stencil_tile_orders(order, variant, tmp_path):
+    """Work orders that visit tiles of blocks (each tile's rhs groups back to
+    back) change only which work-group computes what: results equal the oracle's
+    on a 16x8x8x8 lattice (4x2x2x2 blocks, so several tiles) with a ragged batch."""
+    case("stencil tile order %d variant %d" % (order, variant))
+    dims, block = (16, 8, 8, 8), (4, 4, 4, 4)
+    qmg, lat, U, psi = _setup(dims, block, 0.5, -0.8, 1.0, 2, 3)
+    key = "gfx950|%s|%s|clover=1" % ("x".join(map(str, dims)), "x".join(map(str, block)))
+    entries = ['"%s|dslash|%s|%d": %d' % (key, p, c, variant) for p in ("f64", "f32", "bf16") for c in (0, 1)]
+    entries.append('"%s|ds_order": %d' % (key, order))
+    path = tmp_path / "tune_order.json"
+    path.write_text("{\n" + ",\n".join(entries) + "\n}\n")
+    lat.autotune(str(path))
+    C = oclover.clover_term(U, 1.0)
+    taus = [0.01, -0.2, 0.05]
+    fin = lat.pack(dev(psi), "f64")
+    pin = host(lat.unpack(fin, 3, "f64"))
+    out = host(lat.unpack(lat.apply_Q_shifted(lat.field(3, "f64"), fin, taus, 3, "f64"), 3, "f64"))
+    for k in range(3):
+        assert rel_err(out[k], dirac.apply_Q_shifted(U, pin[k], -0.8, taus[k], C)) < 1e-13
+
+
 @pytest.mark.parametrize("variant", range(11))
 def test_stencil_variants(variant, tmp_path):
     """Every launch variant of the stencil (generic, 4^4 kernels with 1/2/4 rhs per
