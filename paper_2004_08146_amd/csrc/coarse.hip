@@ -110,60 +110,52 @@ template <> __device__ __forceinline__ int mrow<float>(int l, int r) { return 4 
 template <> __device__ __forceinline__ int mrow<double>(int l, int r) { return 4 * r + (l >> 4); }
 
 template <typename S, typename C, int NT>
-__global__ __launch_bounds__(64) void k_coarse_mfma(Geom g, typename PT<C>::stor* out, const typename PT<S>::stor* DcT,
+__global__ __launch_bounds__(64 * NT) void k_coarse_mfma(Geom g, typename PT<C>::stor* out, const typename PT<S>::stor* DcT,
                                                     const typename PT<C>::stor* in, int nrhs, TauArr tau) {
   using R = typename PT<C>::real;
   using AT = typename MAcc<R>::T;
   constexpr int NC = 16 * NT;  // 2 ntv
   __shared__ cpx<R> Bs[NC][16];
   __shared__ cpx<R> Bself[NC][16];
-  const int b = blockIdx.x, n0 = blockIdx.y * 16, l = threadIdx.x;
+  // one wave per 16-row tile t of the output; the waves share the staged inputs
+  const int b = blockIdx.x, n0 = blockIdx.y * 16, tid = threadIdx.x;
+  const int t = tid >> 6, l = tid & 63;
   const int ln = l & 15, lk = l >> 4;
-  AT acc_re[NT], acc_im[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    acc_re[t] = AT{0, 0, 0, 0};
-    acc_im[t] = AT{0, 0, 0, 0};
-  }
+  AT acc_re = AT{0, 0, 0, 0}, acc_im = AT{0, 0, 0, 0};
   const auto* Db = DcT + (int64_t)b * 9 * NC * NC;
 #pragma unroll 1
   for (int d = 0; d < 9; ++d) {
     const int nbk = d == 0 ? b : g.nbr[b * 8 + d - 1];
     __syncthreads();
-    for (int idx = l; idx < NC * 16; idx += 64) {
+    for (int idx = tid; idx < NC * 16; idx += 64 * NT) {
       const int j = idx % NC, n = idx / NC;
       const cpx<R> v = n0 + n < nrhs ? ldcv<R>(in, ((int64_t)(n0 + n) * g.nb + nbk) * NC + j) : czero<R>();
       Bs[j][n] = v;
       if (d == 0) Bself[j][n] = v;
     }
     __syncthreads();
-    const auto* Dd = Db + (int64_t)d * NC * NC;
-#pragma unroll 2
+    const auto* Dd = Db + (int64_t)d * NC * NC + 16 * t + ln;
+#pragma unroll 4
     for (int j0 = 0; j0 < NC; j0 += 4) {
       const cpx<R> bv = Bs[j0 + lk][ln];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const cpx<R> av = ldcv<R>(Dd, (int64_t)(j0 + lk) * NC + 16 * t + ln);
-        acc_re[t] = mfma(av.re, bv.re, acc_re[t]);
-        acc_re[t] = mfma(-av.im, bv.im, acc_re[t]);
-        acc_im[t] = mfma(av.re, bv.im, acc_im[t]);
-        acc_im[t] = mfma(av.im, bv.re, acc_im[t]);
-      }
+      const cpx<R> av = ldcv<R>(Dd, (int64_t)(j0 + lk) * NC);
+      acc_re = mfma(av.re, bv.re, acc_re);
+      acc_re = mfma(-av.im, bv.im, acc_re);
+      acc_im = mfma(av.re, bv.im, acc_im);
+      acc_im = mfma(av.im, bv.re, acc_im);
     }
   }
   const int n = n0 + ln;
   if (n >= nrhs) return;
   const R tn = R(tau.t[n]);
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * t + mrow<R>(l, r);
-      const R g5 = i < NC / 2 ? R(1) : R(-1);
-      const cpx<R> self = Bself[i][ln];
-      const cpx<R> v = {acc_re[t][r] - tn * g5 * self.re, acc_im[t][r] - tn * g5 * self.im};
-      stcv(out, ((int64_t)n * g.nb + b) * NC + i, v);
-    }
+  for (int r = 0; r < 4; ++r) {
+    const int i = 16 * t + mrow<R>(l, r);
+    const R g5 = i < NC / 2 ? R(1) : R(-1);
+    const cpx<R> self = Bself[i][ln];
+    const cpx<R> v = {acc_re[r] - tn * g5 * self.re, acc_im[r] - tn * g5 * self.im};
+    stcv(out, ((int64_t)n * g.nb + b) * NC + i, v);
+  }
 }
 
 template <typename S>
@@ -175,10 +167,10 @@ void capply_mfma(const qmg_ctx* c, int p, void* out, const void* in, const TauAr
   auto go = [&](auto ntc) {
     constexpr int NT = decltype(ntc)::value;
     if (p == QMG_F64)
-      hipLaunchKernelGGL((k_coarse_mfma<S, double, NT>), grid, dim3(64), 0, s, c->g, (double2*)out, (const P*)c->Dc[p],
+      hipLaunchKernelGGL((k_coarse_mfma<S, double, NT>), grid, dim3(64 * NT), 0, s, c->g, (double2*)out, (const P*)c->Dc[p],
                          (const double2*)in, nrhs, tau);
     else
-      hipLaunchKernelGGL((k_coarse_mfma<S, float, NT>), grid, dim3(64), 0, s, c->g, (float2*)out, (const P*)c->Dc[p],
+      hipLaunchKernelGGL((k_coarse_mfma<S, float, NT>), grid, dim3(64 * NT), 0, s, c->g, (float2*)out, (const P*)c->Dc[p],
                          (const float2*)in, nrhs, tau);
   };
   if (nt == 3) go(std::integral_constant<int, 3>{});

@@ -269,6 +269,50 @@ __global__ __launch_bounds__(128) void k_restrict_mfma(Geom g, typename PT<C>::s
     }
 }
 
+// ---- prolongation on MFMA: per block b, chirality h and spin-colour row d,
+// the tile v[n0..n0+15][6h+d][16 sites] = Y^T (16 rhs x ntv) P_hd (ntv x 16
+// sites); Y^T stays in registers for the 96 tiles of (b, h), four waves share them.
+template <typename S, typename C>
+__global__ __launch_bounds__(256) void k_prolong_mfma(Geom g, typename PT<S>::stor* v, const typename PT<S>::stor* P,
+                                                      const typename PT<C>::stor* y, int ntv, int nrhs,
+                                                      int64_t fstride) {
+  using R = typename PT<S>::real;
+  using AT = typename TAcc<R>::T;
+  const int b = blockIdx.x, h = blockIdx.y, n0 = blockIdx.z * 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ln = lane & 15, lk = lane >> 4;
+  const int nc = 2 * ntv, nks = (ntv + 3) >> 2;
+  const bool nok = n0 + ln < nrhs;
+  cpx<R> ya[8];
+#pragma unroll
+  for (int st = 0; st < 8; ++st) {
+    const int j = 4 * st + lk;
+    ya[st] = (st < nks && nok && j < ntv) ? ldcv<R>(y, ((int64_t)(n0 + ln) * g.nb + b) * nc + h * ntv + j)
+                                          : czero<R>();
+  }
+#pragma unroll 1
+  for (int tile = wave; tile < 96; tile += 4) {
+    const int d = tile >> 4, s0 = (tile & 15) << 4;
+    AT cre = AT{0, 0, 0, 0}, cim = AT{0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      if (st < nks) {
+        const int j = 4 * st + lk;
+        const cpx<R> pb = j < ntv ? ldcv<R>(P, pidx(g, ntv, b, h, j, d, s0 + ln)) : czero<R>();
+        cre = tmfma(ya[st].re, pb.re, cre);
+        cre = tmfma(-ya[st].im, pb.im, cre);
+        cim = tmfma(ya[st].re, pb.im, cim);
+        cim = tmfma(ya[st].im, pb.re, cim);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = n0 + trow<R>(lane, r);
+      if (n < nrhs) stcv(v + (int64_t)n * fstride, sidx(g, b, 6 * h + d, s0 + ln), cpx<R>{cre[r], cim[r]});
+    }
+  }
+}
+
 template <typename S>
 void restrict_t(const qmg_ctx* c, void* yc, const void* v, int nrhs, hipStream_t s, int p) {
   using P = typename PT<S>::stor;
@@ -317,6 +361,16 @@ template <typename S>
 void prolong_t(const qmg_ctx* c, void* v, const void* yc, int nrhs, hipStream_t s, int p) {
   using P = typename PT<S>::stor;
   const int bs = 1 << c->g.bs_log;
+  if (nrhs >= c->tune.restrict_mfma_min_rhs && bs == 256 && c->ntv <= 32) {
+    dim3 grid(c->g.nb, 2, (nrhs + 15) / 16);
+    if (p == QMG_F64)
+      hipLaunchKernelGGL((k_prolong_mfma<S, double>), grid, dim3(256), 0, s, c->g, (P*)v, (const P*)c->P[p],
+                         (const double2*)yc, c->ntv, nrhs, (int64_t)field_elems(c));
+    else
+      hipLaunchKernelGGL((k_prolong_mfma<S, float>), grid, dim3(256), 0, s, c->g, (P*)v, (const P*)c->P[p],
+                         (const float2*)yc, c->ntv, nrhs, (int64_t)field_elems(c));
+    return;
+  }
   if (nrhs > 1 && c->tune.transfer_mr) {
     if (p == QMG_F64)
       hipLaunchKernelGGL((k_prolong_mr<S, double>), dim3(c->g.nb), dim3(bs), 0, s, c->g, (P*)v, (const P*)c->P[p],
