@@ -26,6 +26,103 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FLOP_SITE = 1320
+# published MI355X FP32 vector peak; the kernels are built without packed FP32
+# arithmetic, whose issue ceiling is half of it (256 CU x 4 SIMD x 16 lanes x
+# 2 flop x 2.4 GHz = 78.6 TFLOP/s)
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_TFLOPS = 78.6
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_64x32x32x32_16rhs.json")
+# sources that define each profiled kernel: a change to any of them voids its counters
+KERNEL_SOURCES = {
+    "sap_f32": ["paper_2004_08146_amd/csrc/sap.hip", "paper_2004_08146_amd/csrc/qmg_device.h"],
+    "stencil_f32": ["paper_2004_08146_amd/csrc/dslash.hip", "paper_2004_08146_amd/csrc/qmg_device.h"],
+}
+KERNEL_NAMES = {"sap_f32": "k_sap44<float, true, 2>", "stencil_f32": "k_dslash"}
+
+
+def sap_flops_per_site(n_mr):
+    """Algorithmic flops of one SAP half-sweep per site of that colour and per
+    rhs: the residual f - A x (8 hops at 1320, clover 552, diagonal and shift
+    48, subtraction 24) and n_MR block minimal-residual steps, each a block
+    operator (in-block hops only: 6 of 8 on a 4^4 block, 990; clover 552;
+    diagonal 48) plus the MR inner products and updates (336)."""
+    return (1320 + 552 + 48 + 24) + n_mr * (990 + 552 + 48 + 336)
+
+
+def sources_hash(names):
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(key):
+    """HBM bytes per launch of a profiled kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a 1 GiB copy), or
+    None when the kernel's sources changed after the counters were taken."""
+    try:
+        with open(TRAFFIC_JSON) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get("kernels", {}).get(key)
+    if not e or e.get("sources_sha256_16") != sources_hash(KERNEL_SOURCES[key]):
+        return None
+    return e["hbm_bytes_per_launch"]
+
+
+def summarize_pmc(fetch_dir, write_dir, cmd):
+    """Writes the traffic summary from two rocprofv3 --pmc runs of the kernels
+    mode (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  The factors that map
+    the counters to bytes come from the same runs' 1 GiB device copy."""
+    import csv
+    import glob
+
+    def dispatches(d):
+        rows = {}
+        for f in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            for r in csv.DictReader(open(f)):
+                k = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+                rows[k] = rows.get(k, 0.0) + float(r["Counter_Value"])
+        return [(i, n, v) for (i, n), v in sorted(rows.items())]
+
+    def short(n):
+        n = n.replace("(anonymous namespace)::", "")
+        if n.startswith("void "):
+            n = n[5:]
+        return n.split("(")[0]
+
+    fet, wri = dispatches(fetch_dir), dispatches(write_dir)
+    cfet = [v for _, n, v in fet if "copyBuffer" in n and v > 1e5]
+    cwri = [v for _, n, v in wri if "copyBuffer" in n and v > 1e5]
+    cf = (1 << 30) / 1024.0 / np.mean(cfet)
+    cw = (1 << 30) / 1024.0 / np.mean(cwri)
+    out = {"command_fetch": cmd % ("FETCH_SIZE", "fetch"), "command_write": cmd % ("WRITE_SIZE", "write"),
+           "calibration": {"kernel": "__amd_rocclr_copyBuffer (torch copy_ of 1 GiB)", "bytes_read": 1 << 30,
+                           "bytes_written": 1 << 30, "fetch_factor": cf, "write_factor": cw},
+           "note": "per-launch averages over the kernels mode's own timed launches (the last ones of that "
+                   "kernel: after the autotuner), HBM bytes = 1024 * (FETCH_SIZE * fetch_factor + "
+                   "WRITE_SIZE * write_factor)",
+           "kernels": {}}
+    # the kernels mode runs, after the autotuner: f64 1-rhs apply x4, f32 16-rhs apply x4, SAP sweep x3 (6 launches)
+    picks = {"stencil_f32": (lambda n: short(n).startswith("k_dslash") and "float" in short(n)
+                             and "double" not in short(n), 4),
+             "sap_f32": (lambda n: short(n) == KERNEL_NAMES["sap_f32"], 6)}
+    for key, (match, last) in picks.items():
+        fsel = [(i, n, v) for i, n, v in fet if match(n)][-last:]
+        wsel = [(i, n, v) for i, n, v in wri if match(n)][-last:]
+        if not fsel or not wsel:
+            continue
+        f_kib, w_kib = float(np.mean([v for _, _, v in fsel])), float(np.mean([v for _, _, v in wsel]))
+        out["kernels"][key] = {"kernel": short(fsel[-1][1]), "launches": len(fsel),
+                               "fetch_kib": f_kib, "write_kib": w_kib,
+                               "hbm_bytes_per_launch": 1024.0 * (f_kib * cf + w_kib * cw),
+                               "sources_sha256_16": sources_hash(KERNEL_SOURCES[key])}
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def spinor_bytes(prec):
@@ -76,27 +173,30 @@ def cpu_baseline(U, b0, m0, csw, tau, applies_per_rhs):
     distribution), scaled to the full volume (the oracle's cost is linear in
     the volume) and to right-hand sides per second with the number of
     fine-operator applications the GPU solve needed per right-hand side."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import clover, dirac
     sub = (slice(0, U.shape[0] // 2),) + (slice(0, U.shape[1] // 2),) * 3
     Us = np.ascontiguousarray(U[sub])
-    bs = np.ascontiguousarray(b0[sub])
     scale = U[..., 0, 0, 0].size / Us[..., 0, 0, 0].size
-    t0 = time.perf_counter()
-    C = clover.clover_term(Us, csw)
-    t1 = time.perf_counter()
-    dirac.apply_Q_shifted(Us, bs, m0, tau, C)
-    t2 = time.perf_counter()
-    t_apply = (t2 - t1) * scale
+    nap = len(b0)
+    with threadpool_limits(1):
+        C = clover.clover_term(Us, csw)
+        t1 = time.perf_counter()
+        for k in range(nap):
+            dirac.apply_Q_shifted(Us, np.ascontiguousarray(b0[k][sub]), m0, tau, C)
+        t2 = time.perf_counter()
+    t_apply = (t2 - t1) / nap * scale
     V = int(np.prod(U.shape[:4]))
     return {
         "value": 1.0 / (t_apply * applies_per_rhs),
         "unit": "rhs/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": ("one FP64 (Q - tau) apply of 1 rhs on a 1/16 sub-volume (32x16^3) of the clover workload, "
-                   "%.2f s scaled x%d to %.1f s per full apply (clover build not counted), times %.0f "
-                   "fine-operator applications per rhs of the GPU solve" % (t2 - t1, scale, t_apply,
-                                                                          applies_per_rhs)),
+        "sample": ("%d FP64 (Q - tau) applies (one per rhs) on a 1/16 sub-volume (32x16^3) of the clover "
+                   "workload, one thread, %.2f s in all, scaled x%d to %.1f s per full apply (the clover "
+                   "build is not timed), times %.0f fine-operator applications per rhs of the GPU solve"
+                   % (nap, t2 - t1, scale, t_apply, applies_per_rhs)),
         "apply_gflops": FLOP_SITE * V / t_apply / 1e9,
     }
 
@@ -109,8 +209,8 @@ def kernels_mode(args, dims, torch, qmg, unit_links):
     nrhs = args.nrhs
     lat = qmg.Lattice(dims, (4, 4, 4, 4))
     lat.set_gauge(torch.from_numpy(unit_links(dims)).cuda(), args.m0, 1.0)
-    if args.tune_cache:
-        lat.autotune(args.tune_cache)
+    # the same launch choices as the solve bench: a fresh autotune unless told otherwise
+    lat.autotune(args.tune_cache or os.path.join("/tmp", "qmg_tune_k_%d.json" % os.getpid()))
     if args.variant is not None:
         # pin one stencil variant (and the XCD remap) for counter runs
         key = "gfx950|%s|4x4x4x4|clover=1" % "x".join(map(str, dims))
@@ -172,7 +272,14 @@ def main():
     ap.add_argument("--remap", type=int, default=1, help="kernels mode: XCD-aware work-group mapping (with --variant)")
     ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",
                     help="kernels: only a few launches of the hot kernels and a 1 GiB copy (for counter runs)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="write the traffic summary from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of --mode kernels")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc %s --output-format csv -d "
+               "$GRAFT_REPO_ROOT/gpurun_out/pk_%s -o k -- python -u $GRAFT_REPO_ROOT/bench.py --mode kernels")
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], cmd)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -272,23 +379,33 @@ def main():
         byts = apply_bytes_per_site(prec, n, True) * V
         qapply["%s_%drhs" % (prec, n)] = {"ms": ms, "gflops": FLOP_SITE * V * n / ms / 1e6,
                                           "gbps": byts / ms / 1e6, "hbm_frac": byts / ms / 1e6 / HBM_PEAK_GBS}
-    # SAP sweep (FP32, all rhs): the smoother inside every V-cycle
+    # SAP sweep (FP32, all rhs): the smoother inside every V-cycle and the
+    # dominant kernel of the solve; one sweep = two launches (one per colour)
     xs = lat.field(nrhs, "f32")
     fs = lat.field(nrhs, "f32")
-    sap_ms = timer(lambda: lat.sap_smooth(xs, fs, taus, nrhs, 1, 3, "f32"), 5)
+    sap_ms = timer(lambda: lat.sap_smooth(xs, fs, taus, nrhs, 1, 3, "f32"), 10)
     sap_bytes = sap_bytes_per_site("f32", nrhs, True) * V
     del xs, fs
-
-    dom = qapply["f32_%drhs" % nrhs]
-    roofline = {"bound": "hbm", "kernel": "k_dslash<float, clover, Q-tau> (16 rhs)",
-                "achieved": dom["gbps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dom["gbps"] / HBM_PEAK_GBS, "traffic": None}
+    launch_ms = sap_ms / 2
+    sap_flops = sap_flops_per_site(3) * (V // 2) * nrhs
+    achieved = sap_flops / launch_ms / 1e9
+    roofline = {"bound": "alu", "kernel": "k_sap44<float, clover, 2 rhs slots>: one colour's half-sweep, 16 rhs",
+                "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic_for("sap_f32"),
+                "launch_ms": launch_ms, "flops_per_launch": sap_flops,
+                "flop_per_site_rhs": sap_flops_per_site(3),
+                "frac_of_nonpacked_issue_peak": achieved / FP32_NONPACKED_TFLOPS}
+    st = qapply["f32_%drhs" % nrhs]
+    roofline_stencil = {"bound": "hbm", "kernel": "stencil (Q - tau), FP32, 16 rhs", "achieved": st["gbps"],
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": st["gbps"] / HBM_PEAK_GBS,
+                        "traffic": traffic_for("stencil_f32"), "launch_ms": st["ms"],
+                        "alg_bytes_per_launch": apply_bytes_per_site("f32", nrhs, True) * V}
 
     # fine-operator applications per rhs: FGMRES apply + nu * (1 residual + n_MR block applies)
     applies = float(np.mean([s["iters"] * (1 + 3 * 4) + s["restarts"] + 1 for s in all_stats[-1][1]]))
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(U, b[0], m0, csw, taus[0], applies)
+        cpu = cpu_baseline(U, b[:8], m0, csw, taus[0], applies)
 
     line = {
         "metric": "Q-apply GFLOP/s & HBM GB/s; shifted-solve time mixed vs FP64 at 1e-10 rel. residual",
@@ -309,6 +426,7 @@ def main():
         "q_apply": qapply,
         "sap_sweep_f32": {"ms": sap_ms, "gbps": sap_bytes / sap_ms / 1e6, "hbm_frac": sap_bytes / sap_ms / 1e6 / HBM_PEAK_GBS},
         "roofline": roofline,
+        "roofline_stencil": roofline_stencil,
         "autotune": tuning,
         "cpu_baseline": cpu,
     }
