@@ -189,6 +189,55 @@ qmg_status qmg_solve_shifted(qmg_ctx* ctx, void* x, const void* b, const double*
 qmg_status qmg_gauge_force(qmg_ctx* ctx, double* dU, double* dUbar, const void* phi,
                            const void* x, hipStream_t stream);
 
+/* ---- GD-lambdaAMG eigensolver (Alg. GD-lambdaAMG, Sec. 3.3; defaults from
+ * the paper's parameter table, see qmg_default_eig_params). */
+typedef struct {
+  int m_min;           /* search-space size kept at a thick restart (30) */
+  int m_max;           /* search-space size that triggers a restart (50) */
+  double tol;          /* lock when ||Q u - theta u|| <= tol, ||u|| = 1 (1e-8) */
+  int maxiter;         /* outer iterations (expansions) */
+  double inner_tol;    /* correction-equation relative residual (0.1) */
+  int inner_maxiter;   /* FGMRES iterations per correction equation (5) */
+  int update_interp;   /* 1: rebuild P and D_c from the ntv converged eigenvectors
+                          closest to the current target after each lock */
+  qmg_params solve;    /* inner solver settings (precision, smoother, coarse steps);
+                          tol, maxiter and use_graph are overridden */
+} qmg_eig_params;
+
+typedef struct {
+  int iters;           /* outer iterations (search-space expansions) */
+  int converged;       /* eigenpairs locked */
+  int inner_iters;     /* FGMRES iterations over all correction equations */
+  int interp_updates;  /* interpolation rebuilds */
+  double seconds;      /* wall time */
+} qmg_eig_stats;
+
+qmg_eig_params qmg_default_eig_params(void);
+
+/* Eigenpairs of Q = Gamma5 D of smallest modulus by generalized Davidson with
+ * harmonic Ritz extraction (the pencil (QV)^H (QV) s = theta (QV)^H V s),
+ * locking, thick restarts and multigrid-preconditioned correction equations
+ * (D - theta Gamma5) t = Gamma5 r (Alg. GD-lambdaAMG, Sec. 3.3).
+ *   lambda: host array [nev], the Rayleigh quotients u^H Q u of the locked
+ *           vectors, in the order they converged;
+ *   X:      device, nev internal F64 fields (output, orthonormal);
+ *   V0:     device, n0 internal F64 fields spanning the initial space (for
+ *           example the test vectors of qmg_setup_mg; may be NULL with n0 = 0);
+ *   t0:     device, one internal F64 field, the first expansion vector.
+ * Needs qmg_set_gauge (and, for a two-level inner solver and interpolation
+ * updates, qmg_set_test_vectors or qmg_setup_mg).  Synchronises the stream.
+ * Returns QMG_NOT_CONVERGED when maxiter ends the run early (lambda and X hold
+ * stats->converged pairs). */
+qmg_status qmg_eigensolve(qmg_ctx* ctx, int nev, double* lambda, void* X, const void* V0, int n0,
+                          const void* t0, const qmg_eig_params* params, qmg_eig_stats* stats,
+                          hipStream_t stream);
+
+/* Host-side dense Hermitian eigensolver used for the harmonic Ritz pencil
+ * (cyclic Jacobi): a is m x m, column-major, interleaved re/im doubles; w gets
+ * the eigenvalues in ascending order, z (m x m, same layout) the eigenvectors
+ * as columns.  Pure host code (no device needed).  QMG_E_ARG on bad sizes. */
+qmg_status qmg_hermitian_eig(int m, const double* a, double* w, double* z);
+
 /* Time the launch variants of the hot kernels for this context's shape and
  * pick the fastest; results are cached in a JSON file keyed by device
  * architecture and lattice shape (path may be NULL: no file). */

@@ -165,6 +165,35 @@ qmg_params qmg_default_params(void) {
   return p;
 }
 
+qmg_eig_params qmg_default_eig_params(void) {
+  qmg_eig_params e;
+  e.m_min = 30;
+  e.m_max = 50;
+  e.tol = 1e-8;
+  e.maxiter = 10000;
+  e.inner_tol = 0.1;
+  e.inner_maxiter = 5;
+  e.update_interp = 1;
+  e.solve = qmg_default_params();
+  e.solve.mg_prec = QMG_F32;
+  e.solve.restart = 5;
+  return e;
+}
+
+qmg_status qmg_hermitian_eig(int m, const double* a, double* w, double* z) {
+  if (m < 1 || m > 4096 || !a || !w || !z) return QMG_E_ARG;
+  std::vector<std::complex<double>> A((size_t)m * m), Z;
+  for (size_t i = 0; i < A.size(); ++i) A[i] = {a[2 * i], a[2 * i + 1]};
+  std::vector<double> ev;
+  herm_eig(m, A, ev, Z);
+  for (int k = 0; k < m; ++k) w[k] = ev[k];
+  for (size_t i = 0; i < Z.size(); ++i) {
+    z[2 * i] = Z[i].real();
+    z[2 * i + 1] = Z[i].imag();
+  }
+  return QMG_OK;
+}
+
 qmg_status qmg_create(qmg_ctx** out, const int dims[4], const int block[4], int device) {
   if (!out || !dims || !block) return QMG_E_ARG;
   *out = nullptr;
@@ -497,6 +526,22 @@ qmg_status qmg_gauge_force(qmg_ctx* c, double* dU, double* dUbar, const void* ph
   if (!dU || !dUbar || !phi || !x) return set_err(c, QMG_E_ARG, "gauge_force: null pointer");
   hipSetDevice(c->device);
   return hipchk(c, launch_force(c, dU, dUbar, phi, x, s), "gauge_force");
+}
+
+qmg_status qmg_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const void* V0, int n0, const void* t0,
+                          const qmg_eig_params* prm, qmg_eig_stats* st, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(need_gauge(c));
+  QMG_TRY(need_sap(c));
+  const qmg_eig_params p = prm ? *prm : qmg_default_eig_params();
+  if (nev < 1 || !lambda || !X || !t0 || n0 < 0 || (n0 > 0 && !V0))
+    return set_err(c, QMG_E_ARG, "eigensolve: bad arguments");
+  if (p.m_max < 2 || p.m_min < 1 || p.m_min >= p.m_max || n0 >= p.m_max || !(p.tol > 0) || p.maxiter < 1 ||
+      !(p.inner_tol > 0) || p.inner_maxiter < 1)
+    return set_err(c, QMG_E_ARG, "eigensolve: bad parameters");
+  QMG_TRY(check_prec(c, p.solve.mg_prec));
+  hipSetDevice(c->device);
+  return solver_eigensolve(c, nev, lambda, X, V0, n0, t0, &p, st, s);
 }
 
 qmg_status qmg_autotune(qmg_ctx* c, const char* path) {

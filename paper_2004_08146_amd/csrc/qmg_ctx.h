@@ -1,6 +1,7 @@
 // Host-side context and the launchers each kernel file provides.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <complex>
 #include <map>
 #include <string>
 #include <vector>
@@ -148,6 +149,10 @@ qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const 
 // z = M r; z is written in precision zprec (FP64, or the preconditioner's own precision)
 qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs,
                          const qmg_params* prm, int* coarse_iters, hipStream_t s, int zprec = QMG_F64);
+qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const void* V0, int n0,
+                             const void* t0, const qmg_eig_params* prm, qmg_eig_stats* stats, hipStream_t s);
+void herm_eig(int m, std::vector<std::complex<double>> a, std::vector<double>& w,
+              std::vector<std::complex<double>>& z);
 qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, int nrhs,
                          const qmg_params* prm, qmg_stats* st, hipStream_t s);
 qmg_status build_mg(qmg_ctx* c, const void* W, int ntv, hipStream_t s);

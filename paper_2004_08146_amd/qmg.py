@@ -46,6 +46,20 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class EigParams(ctypes.Structure):
+    _fields_ = [("m_min", ctypes.c_int), ("m_max", ctypes.c_int), ("tol", ctypes.c_double),
+                ("maxiter", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxiter", ctypes.c_int),
+                ("update_interp", ctypes.c_int), ("solve", Params)]
+
+
+class EigStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("inner_iters", ctypes.c_int),
+                ("interp_updates", ctypes.c_int), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _d = ctypes.c_double
@@ -76,6 +90,10 @@ _SIG = {
     "qmg_solve_shifted": ([_vp, _vp, _vp, _dp, _i, ctypes.POINTER(Params), ctypes.POINTER(Stats), _vp], _i),
     "qmg_gauge_force": ([_vp, _vp, _vp, _vp, _vp, _vp], _i),
     "qmg_autotune": ([_vp, ctypes.c_char_p], _i),
+    "qmg_default_eig_params": ([], EigParams),
+    "qmg_eigensolve": ([_vp, _i, _dp, _vp, _vp, _i, _vp, ctypes.POINTER(EigParams), ctypes.POINTER(EigStats),
+                        _vp], _i),
+    "qmg_hermitian_eig": ([_i, _dp, _dp, _dp], _i),
 }
 for _name, (_args, _res) in _SIG.items():
     _f = getattr(_lib, _name)
@@ -92,6 +110,33 @@ def default_params(**kw):
             v = _PREC[v]
         setattr(p, k, v)
     return p
+
+
+def default_eig_params(**kw):
+    """GD-lambdaAMG parameters; keys of the inner solver go in solve={...}."""
+    p = _lib.qmg_default_eig_params()
+    for k, v in kw.items():
+        if k == "solve":
+            for kk, vv in v.items():
+                setattr(p.solve, kk, _PREC[vv] if kk == "mg_prec" else vv)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def hermitian_eig(a):
+    """Eigenvalues (ascending) and eigenvectors of a Hermitian matrix with the
+    library's host Jacobi solver (the harmonic-Ritz step of the eigensolver)."""
+    import numpy as np
+    a = np.asarray(a, dtype=np.complex128)
+    m = a.shape[0]
+    af = np.asfortranarray(a).ravel(order="F").view(np.float64).copy()
+    w = np.zeros(m)
+    z = np.zeros(2 * m * m)
+    st = _lib.qmg_hermitian_eig(m, af.ctypes.data_as(_dp), w.ctypes.data_as(_dp), z.ctypes.data_as(_dp))
+    if st != 0:
+        raise QmgError(st, "hermitian_eig")
+    return w, z.view(np.complex128).reshape(m, m, order="F")
 
 
 def _ptr(t):
@@ -260,6 +305,18 @@ class Lattice:
         self._check(_lib.qmg_gauge_force(self._h, _ptr(G), _ptr(Gb), _ptr(phi), _ptr(x), _stream()),
                     "gauge_force")
         return G, Gb
+
+    def eigensolve(self, nev, X, t0, V0=None, n0=0, params=None):
+        """GD-lambdaAMG: returns (status, eigenvalues (numpy, lock order), stats dict);
+        X receives nev internal F64 eigenvector fields."""
+        import numpy as np
+        params = params or default_eig_params()
+        lam = np.zeros(nev)
+        stats = EigStats()
+        st = self._check(_lib.qmg_eigensolve(self._h, nev, lam.ctypes.data_as(_dp), _ptr(X),
+                                             _ptr(V0) if V0 is not None else None, n0, _ptr(t0),
+                                             ctypes.byref(params), ctypes.byref(stats), _stream()), "eigensolve")
+        return st, lam[:stats.converged], stats.as_dict()
 
     def autotune(self, cache_json_path=None):
         p = cache_json_path.encode() if cache_json_path else None
