@@ -49,6 +49,48 @@ def sap_flops_per_site(n_mr):
     return (1320 + 552 + 48 + 24) + n_mr * (990 + 552 + 48 + 336)
 
 
+def eigensolver_run(args, torch, qmg, random_links, seed_for, device_gaussian_spinors, m0):
+    """GD-lambdaAMG (Alg. GD-lambdaAMG) on a second synthetic lattice: setup with
+    24 test vectors, then nev eigenpairs of Q of smallest modulus to a 1e-8
+    residual with the paper's default parameters (m_min 30, m_max 50, inner
+    FGMRES to 0.1 or 5 iterations, coarse tolerance 0.5, interpolation
+    updates), FP32 V-cycle.  Residuals are recomputed with the library's
+    operator."""
+    dims = tuple(int(v) for v in args.eig_dims.split(","))
+    t0 = time.time()
+    U = random_links(dims, 0.5, seed_for(4, "U"))
+    lat = qmg.Lattice(dims, (4, 4, 4, 4))
+    lat.set_gauge(torch.from_numpy(U).cuda(), m0, 1.0)
+    del U
+    ntv = 24
+    W = lat.pack(device_gaussian_spinors(dims, ntv, seed_for(4, "W")))
+    lat.setup_mg(W, ntv, setup_iters=6, smooth=4)
+    lat.autotune(None)
+    t0v = lat.pack(device_gaussian_spinors(dims, 1, seed_for(4, "x")))
+    X = lat.field(args.eig_nev)
+    prm = qmg.default_eig_params(block=args.eig_block, solve={"mg_prec": "f32"})
+    torch.cuda.synchronize()
+    print("[bench] eigensolver inputs and setup %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    st, lam, stats = lat.eigensolve(args.eig_nev, X, t0v, V0=W, n0=ntv, params=prm)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t1
+    fb = lat.field_bytes()
+    res = []
+    for k in range(len(lam)):
+        x = X[k * fb:(k + 1) * fb]
+        r = lat.apply_Q_shifted(lat.field(1), x, [float(lam[k])], 1)
+        res.append(float(np.sqrt(max(0.0, lat.field_dot(r, r)[0].real))))
+    print("[bench] eigensolver %.1f s: %d pairs, status %d" % (sec, len(lam), st), file=sys.stderr, flush=True)
+    return {"workload": "%s clover (c_sw 1, m0 %.2f), %d eigenpairs of Q of smallest |lambda|, tol 1e-8"
+                        % ("x".join(map(str, dims)), m0, args.eig_nev),
+            "seconds": sec, "status": st, "eigenpairs_per_s": len(lam) / sec,
+            "outer_iters": stats["iters"], "inner_fgmres_iters": stats["inner_iters"],
+            "interp_updates": stats["interp_updates"], "block": args.eig_block,
+            "max_residual": max(res) if res else None,
+            "lambda_abs_range": [float(np.min(np.abs(lam))), float(np.max(np.abs(lam)))] if len(lam) else None}
+
+
 def sources_hash(names):
     import hashlib
     h = hashlib.sha256()
@@ -272,6 +314,10 @@ def main():
     ap.add_argument("--remap", type=int, default=1, help="kernels mode: XCD-aware work-group mapping (with --variant)")
     ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",
                     help="kernels: only a few launches of the hot kernels and a 1 GiB copy (for counter runs)")
+    ap.add_argument("--eig-dims", type=str, default="32,32,32,32",
+                    help="lattice of the GD-lambdaAMG eigensolver measurement ('' to skip)")
+    ap.add_argument("--eig-nev", type=int, default=20, help="eigenpairs in the eigensolver measurement")
+    ap.add_argument("--eig-block", type=int, default=1, help="targets per outer step of the eigensolver")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="write the traffic summary from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of --mode kernels")
     args = ap.parse_args()
@@ -401,6 +447,12 @@ def main():
                         "traffic": traffic_for("stencil_f32"), "launch_ms": st["ms"],
                         "alg_bytes_per_launch": apply_bytes_per_site("f32", nrhs, True) * V}
 
+    eig = None
+    if args.eig_dims:
+        del lat
+        torch.cuda.empty_cache()
+        eig = eigensolver_run(args, torch, qmg, random_links, seed_for, device_gaussian_spinors, -0.8)
+
     # fine-operator applications per rhs: FGMRES apply + nu * (1 residual + n_MR block applies)
     applies = float(np.mean([s["iters"] * (1 + 3 * 4) + s["restarts"] + 1 for s in all_stats[-1][1]]))
     cpu = None
@@ -427,6 +479,7 @@ def main():
         "sap_sweep_f32": {"ms": sap_ms, "gbps": sap_bytes / sap_ms / 1e6, "hbm_frac": sap_bytes / sap_ms / 1e6 / HBM_PEAK_GBS},
         "roofline": roofline,
         "roofline_stencil": roofline_stencil,
+        "eigensolver": eig,
         "autotune": tuning,
         "cpu_baseline": cpu,
     }

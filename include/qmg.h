@@ -200,6 +200,10 @@ typedef struct {
   int inner_maxiter;   /* FGMRES iterations per correction equation (5) */
   int update_interp;   /* 1: rebuild P and D_c from the ntv converged eigenvectors
                           closest to the current target after each lock */
+  int block;           /* targets per outer step (1..16): the correction equations of
+                          the `block` unlocked harmonic Ritz pairs of smallest |theta|
+                          are solved as one batched multi-shift solve and all of them
+                          expand the space (1: one target per step, as Alg. GD-lambdaAMG) */
   qmg_params solve;    /* inner solver settings (precision, smoother, coarse steps);
                           tol, maxiter and use_graph are overridden */
 } qmg_eig_params;
@@ -226,6 +230,10 @@ qmg_eig_params qmg_default_eig_params(void);
  *   t0:     device, one internal F64 field, the first expansion vector.
  * Needs qmg_set_gauge (and, for a two-level inner solver and interpolation
  * updates, qmg_set_test_vectors or qmg_setup_mg).  Synchronises the stream.
+ * Once nev pairs are locked the iteration goes on while the smallest unlocked
+ * |theta| lies below the largest locked |lambda| by more than its residual; a
+ * pair that then converges replaces that largest one.  Needs m_min + block <=
+ * m_max and n0 + 1 <= m_max.
  * Returns QMG_NOT_CONVERGED when maxiter ends the run early (lambda and X hold
  * stats->converged pairs). */
 qmg_status qmg_eigensolve(qmg_ctx* ctx, int nev, double* lambda, void* X, const void* V0, int n0,

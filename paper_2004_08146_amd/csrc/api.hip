@@ -174,6 +174,7 @@ qmg_eig_params qmg_default_eig_params(void) {
   e.inner_tol = 0.1;
   e.inner_maxiter = 5;
   e.update_interp = 1;
+  e.block = 1;
   e.solve = qmg_default_params();
   e.solve.mg_prec = QMG_F32;
   e.solve.restart = 5;
@@ -536,8 +537,8 @@ qmg_status qmg_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const vo
   const qmg_eig_params p = prm ? *prm : qmg_default_eig_params();
   if (nev < 1 || !lambda || !X || !t0 || n0 < 0 || (n0 > 0 && !V0))
     return set_err(c, QMG_E_ARG, "eigensolve: bad arguments");
-  if (p.m_max < 2 || p.m_min < 1 || p.m_min >= p.m_max || n0 >= p.m_max || !(p.tol > 0) || p.maxiter < 1 ||
-      !(p.inner_tol > 0) || p.inner_maxiter < 1)
+  if (p.m_max < 2 || p.m_min < 1 || p.block < 1 || p.block > 16 || p.m_min + p.block > p.m_max || n0 >= p.m_max ||
+      !(p.tol > 0) || p.maxiter < 1 || !(p.inner_tol > 0) || p.inner_maxiter < 1)
     return set_err(c, QMG_E_ARG, "eigensolve: bad parameters");
   QMG_TRY(check_prec(c, p.solve.mg_prec));
   hipSetDevice(c->device);

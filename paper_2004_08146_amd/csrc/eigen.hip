@@ -17,6 +17,8 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 #include <vector>
 
@@ -164,20 +166,21 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
   auto tstart = std::chrono::steady_clock::now();
   const int64_t n = (int64_t)field_elems(c);
   const size_t fb = (size_t)n * 16;
-  const int mmax = prm->m_max, mmin = prm->m_min;
+  const int mmax = prm->m_max, mmin = prm->m_min, nblk = prm->block;
   auto fld = [&](void* base, int j) { return (void*)((char*)base + (size_t)j * fb); };
   void* V = ws_get(c, "eg_V", fb * (mmax + 1));
   void* W = ws_get(c, "eg_W", fb * (mmax + 1));
   void* T = ws_get(c, "eg_T", fb * (mmax + 1));
-  void* t = ws_get(c, "eg_t", fb);
-  void* u = ws_get(c, "eg_u", fb);
-  void* Qu = ws_get(c, "eg_Qu", fb);
-  void* r = ws_get(c, "eg_r", fb);
+  // per target of a block step: correction t, Ritz vector u, Q u, residual r
+  void* Tc = ws_get(c, "eg_t", fb * nblk);
+  void* U = ws_get(c, "eg_u", fb * nblk);
+  void* QU = ws_get(c, "eg_Qu", fb * nblk);
+  void* R = ws_get(c, "eg_r", fb * nblk);
   const int nmax = std::max(std::max(mmax, nev), c->ntv) + 2;
   double* d_dots = (double*)ws_get(c, "eg_dots", sizeof(double) * 2 * nmax);
   double* d_part = (double*)ws_get(c, "eg_part", sizeof(double) * multidot_partial_doubles(n, nmax, 1));
   double* d_coef = (double*)ws_get(c, "eg_coef", sizeof(double) * 2 * nmax);
-  if (!V || !W || !T || !t || !u || !Qu || !r || !d_dots || !d_part || !d_coef)
+  if (!V || !W || !T || !Tc || !U || !QU || !R || !d_dots || !d_part || !d_coef)
     return set_err(c, QMG_E_NOMEM, "out of device memory (eigensolver)");
   std::vector<double> hbuf(2 * nmax);
   const double zero_tau = 0.0;
@@ -291,7 +294,7 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
     return ov > 0.5;
   };
   // u = V s, Qu = W s, r = Qu - theta u (u normalised); returns ||r||
-  auto ritz = [&](const std::vector<cd>& sv, double th, double& rn) -> qmg_status {
+  auto ritz = [&](const std::vector<cd>& sv, double th, void* u, void* Qu, void* r, double& rn) -> qmg_status {
     hipError_t e = launch_fill_zero(u, fb, s);
     if (e == hipSuccess) e = launch_fill_zero(Qu, fb, s);
     if (e != hipSuccess) return hip_err(c, e, "eigensolver zero");
@@ -309,25 +312,7 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
     return st;
   };
 
-  // ---- initial space: V0 orthonormalised, then t0
-  for (int j = 0; j < n0 && m < mmax; ++j) {
-    qmg_status st = copy(t, (const char*)V0 + (size_t)j * fb);
-    double nrm = 0;
-    if (st == QMG_OK) st = orth(t, V, m, nrm);
-    if (st != QMG_OK) return st;
-    if (nrm > 1e-10) {
-      st = append(t, nrm);
-      if (st != QMG_OK) return st;
-    }
-  }
-  qmg_status st = copy(t, t0);
-  if (st != QMG_OK) return st;
-  qmg_params ip = prm->solve;
-  ip.tol = prm->inner_tol;
-  ip.maxiter = prm->inner_maxiter;
-  ip.use_graph = 0;  // every correction equation has its own shift
   std::vector<double> lam;
-  int iters = 0, inner = 0, updates = 0;
   // largest |lambda| among the locked pairs (the one a smaller pair replaces)
   auto worst = [&]() {
     int w = 0;
@@ -335,68 +320,108 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
       if (std::abs(lam[k]) > std::abs(lam[w])) w = k;
     return w;
   };
-  bool done = false;
-  while (!done && iters < prm->maxiter) {
-    // expand: t <- (I - V V^H)(I - X X^H) t, v_m = t / ||t||
+  // lock the Ritz pair (u, Qu) of coefficient vector sv: u is first made
+  // orthogonal to the locked vectors (a Ritz vector formed before the last
+  // lock overlaps it by about residual / gap); lambda = u^H Q u
+  auto lock = [&](void* u, void* Qu, const std::vector<cd>& sv) -> qmg_status {
+    double un = 0;
+    qmg_status st = orth(u, nullptr, 0, un);
+    if (st != QMG_OK) return st;
+    if (!(un > 0)) return set_err(c, QMG_E_NUMERIC, "converged vector lies in the locked space");
+    st = scale(u, u, cd(1.0 / un));
+    if (st == QMG_OK) st = applyQ(Qu, u);
+    std::vector<cd> rq;
+    if (st == QMG_OK) st = dots(u, 1, Qu, rq);
+    const int slot = nconv < nev ? nconv : worst();
+    if (st == QMG_OK) st = copy(fld(X, slot), u);
+    if (st != QMG_OK) return st;
+    if (nconv < nev) {
+      lam.push_back(rq[0].real());
+      ++nconv;
+    } else {
+      lam[slot] = rq[0].real();
+    }
+    XV.push_back(sv);
+    return QMG_OK;
+  };
+
+  // ---- initial space: V0 orthonormalised; the first expansion vector is t0
+  for (int j = 0; j < n0 && m < mmax; ++j) {
+    qmg_status st = copy(fld(Tc, 0), (const char*)V0 + (size_t)j * fb);
     double nrm = 0;
-    st = orth(t, V, m, nrm);
+    if (st == QMG_OK) st = orth(fld(Tc, 0), V, m, nrm);
     if (st != QMG_OK) return st;
-    if (!(nrm > 1e-14)) return set_err(c, QMG_E_NUMERIC, "eigensolver expansion vector vanished");
-    st = append(t, nrm);
-    if (st != QMG_OK) return st;
-    ++iters;
-    // target: the unlocked harmonic Ritz pair of smallest |theta|
-    std::vector<double> th;
-    std::vector<std::vector<cd>> S;
-    int pick = -1;
-    double rn = 0;
-    bool locked_one = true, newly_locked = false;
-    while (locked_one) {
-      locked_one = false;
-      st = pencil(th, S);
+    if (nrm > 1e-10) {
+      st = append(fld(Tc, 0), nrm);
       if (st != QMG_OK) return st;
-      pick = -1;
-      for (size_t k = 0; k < th.size(); ++k)
-        if (!is_locked(S[k])) { pick = (int)k; break; }
-      if (pick < 0) return set_err(c, QMG_E_NUMERIC, "no unlocked harmonic Ritz pair");
-      st = ritz(S[pick], th[pick], rn);
+    }
+  }
+  qmg_status st = copy(fld(Tc, 0), t0);
+  if (st != QMG_OK) return st;
+  int nt = 1;
+  qmg_params ip = prm->solve;
+  ip.tol = prm->inner_tol;
+  ip.maxiter = prm->inner_maxiter;
+  ip.use_graph = 0;  // every correction equation has its own shift
+  int iters = 0, inner = 0, updates = 0;
+  bool done = false;
+  std::vector<qmg_stats> ist(nblk);
+  // QMG_PROGRESS=1: one line on stderr every 25 outer iterations (long runs)
+  const char* pe = std::getenv("QMG_PROGRESS");
+  const bool progress = pe && pe[0] == '1';
+  while (!done && iters < prm->maxiter) {
+    if (progress && iters % 25 == 0)
+      std::fprintf(stderr, "[eigensolve] outer %d locked %d inner %d updates %d\n", iters, nconv, inner, updates);
+    // expand with the corrections: t <- (I - V V^H)(I - X X^H) t, v_m = t / ||t||
+    const int m_before = m;
+    for (int j = 0; j < nt && m < mmax; ++j) {
+      double nrm = 0;
+      st = orth(fld(Tc, j), V, m, nrm);
       if (st != QMG_OK) return st;
-      // with nev pairs locked, go on only while the target lies below the
-      // largest locked |lambda| by more than its residual (greedy locking can
-      // take a slightly larger pair first); a pair that then converges
-      // replaces that largest one
-      if (nconv >= nev && std::abs(th[pick]) - rn >= std::abs(lam[worst()])) {
-        done = true;
-        break;
-      }
-      if (rn <= prm->tol) {
-        // lock (u, rho) with the Rayleigh quotient rho = u^H Q u; u is first
-        // made orthogonal to the locked vectors (a Ritz vector formed before
-        // the last lock overlaps it by about residual / gap)
-        double un = 0;
-        st = orth(u, nullptr, 0, un);
+      if (nrm > 1e-12) {
+        st = append(fld(Tc, j), nrm);
         if (st != QMG_OK) return st;
-        if (!(un > 0)) return set_err(c, QMG_E_NUMERIC, "converged vector lies in the locked space");
-        st = scale(u, u, cd(1.0 / un));
-        if (st == QMG_OK) st = applyQ(Qu, u);
-        std::vector<cd> rq;
-        if (st == QMG_OK) st = dots(u, 1, Qu, rq);
-        const int slot = nconv < nev ? nconv : worst();
-        if (st == QMG_OK) st = copy(fld(X, slot), u);
-        if (st != QMG_OK) return st;
-        if (nconv < nev) {
-          lam.push_back(rq[0].real());
-          ++nconv;
-        } else {
-          lam[slot] = rq[0].real();
-        }
-        XV.push_back(S[pick]);
-        locked_one = true;
-        newly_locked = true;
       }
     }
+    if (m == m_before) return set_err(c, QMG_E_NUMERIC, "eigensolver expansion vectors vanished");
+    ++iters;
+    // targets: the (up to) nblk unlocked harmonic Ritz pairs of smallest |theta|
+    std::vector<double> th;
+    std::vector<std::vector<cd>> S;
+    std::vector<int> cand;
+    std::vector<double> rns;
+    bool newly_locked = false;
+    while (true) {
+      st = pencil(th, S);
+      if (st != QMG_OK) return st;
+      cand.clear();
+      for (size_t k = 0; k < th.size() && (int)cand.size() < nblk; ++k)
+        if (!is_locked(S[k])) cand.push_back((int)k);
+      if (cand.empty()) return set_err(c, QMG_E_NUMERIC, "no unlocked harmonic Ritz pair");
+      rns.assign(cand.size(), 0.0);
+      bool relock = false;
+      for (size_t i = 0; i < cand.size(); ++i) {
+        st = ritz(S[cand[i]], th[cand[i]], fld(U, (int)i), fld(QU, (int)i), fld(R, (int)i), rns[i]);
+        if (st != QMG_OK) return st;
+        // with nev pairs locked, go on only while the first target lies below
+        // the largest locked |lambda| by more than its residual (greedy
+        // locking can take a slightly larger pair first); a pair that then
+        // converges replaces that largest one
+        if (i == 0 && nconv >= nev && std::abs(th[cand[0]]) - rns[0] >= std::abs(lam[worst()])) {
+          done = true;
+          break;
+        }
+        if (rns[i] <= prm->tol) {
+          st = lock(fld(U, (int)i), fld(QU, (int)i), S[cand[i]]);
+          if (st != QMG_OK) return st;
+          relock = newly_locked = true;
+          break;  // the candidate list changes: form it again
+        }
+      }
+      if (done || !relock) break;
+    }
     if (done) break;
-    const double theta = th[pick];
+    const double theta = th[cand[0]];
     // after a lock: rebuild the interpolation from the ntv converged
     // eigenvectors closest to the new target theta
     if (newly_locked && prm->update_interp && c->ntv > 0 && nconv >= c->ntv) {
@@ -414,15 +439,17 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
       if (st != QMG_OK) return st;
       ++updates;
     }
-    // correction equation (Q - theta) t = r, approximately
-    qmg_stats ist;
-    st = launch_fill_zero(t, fb, s) == hipSuccess ? QMG_OK : hip_err(c, hipGetLastError(), "zero");
-    if (st != QMG_OK) return st;
-    st = solver_fgmres(c, t, r, &theta, 1, &ip, &ist, s);
+    // correction equations (Q - theta_i) t_i = r_i for all targets, as one
+    // batched multi-shift solve
+    nt = (int)cand.size();
+    std::vector<double> taus(nt);
+    for (int i = 0; i < nt; ++i) taus[i] = th[cand[i]];
+    st = solver_fgmres(c, Tc, R, taus.data(), nt, &ip, ist.data(), s);
     if (st < 0) return st;
-    inner += ist.iters;
-    // thick restart: keep the m_min unlocked harmonic Ritz vectors of smallest |theta|
-    if (m >= mmax) {
+    for (int i = 0; i < nt; ++i) inner += ist[i].iters;
+    // thick restart: keep the m_min unlocked harmonic Ritz vectors of smallest
+    // |theta| when the next expansion would not fit
+    if (m + nt > mmax) {
       st = pencil(th, S);
       if (st != QMG_OK) return st;
       int kept = 0;

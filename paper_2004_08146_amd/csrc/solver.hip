@@ -351,11 +351,14 @@ static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* 
     e = launch_restrict(c, p, rc, rp, nrhs, s);
     if (e != hipSuccess) return hip_err(c, e, "restrict");
     int it = 0;
-    qmg_status st = graph_safe ? coarse_gmres_device(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, s)
-                               : solver_coarse_gmres(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, prm->coarse_tol,
-                                                     &it, s);
+    // a fixed number of coarse steps (graph mode, or coarse_tol <= 0) runs the
+    // device-resident GMRES, which never waits for the host
+    const bool fixed = graph_safe || !(prm->coarse_tol > 0);
+    qmg_status st = fixed ? coarse_gmres_device(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, s)
+                          : solver_coarse_gmres(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, prm->coarse_tol,
+                                                &it, s);
     if (st != QMG_OK) return st;
-    if (graph_safe) it = prm->coarse_maxiter;
+    if (fixed) it = prm->coarse_maxiter;
     if (coarse_iters) *coarse_iters += it;
     e = launch_prolong(c, p, zp, yc, nrhs, s);
     if (e != hipSuccess) return hip_err(c, e, "prolong");

@@ -49,7 +49,7 @@ class Stats(ctypes.Structure):
 class EigParams(ctypes.Structure):
     _fields_ = [("m_min", ctypes.c_int), ("m_max", ctypes.c_int), ("tol", ctypes.c_double),
                 ("maxiter", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxiter", ctypes.c_int),
-                ("update_interp", ctypes.c_int), ("solve", Params)]
+                ("update_interp", ctypes.c_int), ("block", ctypes.c_int), ("solve", Params)]
 
 
 class EigStats(ctypes.Structure):

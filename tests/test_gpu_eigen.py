@@ -11,7 +11,7 @@ from synth import random_links, random_spinors, seed_for
 pytestmark = pytest.mark.gpu
 
 
-def _run(dims, block, m0, ntv, nev, mmin, mmax, cfg, update=1, seed=4):
+def _run(dims, block, m0, ntv, nev, mmin, mmax, cfg, update=1, seed=4, nblk=1):
     qmg = need_gpu()
     U = random_links(dims, 0.5, seed_for(cfg, "U"))
     lat = qmg.Lattice(dims, block)
@@ -20,7 +20,7 @@ def _run(dims, block, m0, ntv, nev, mmin, mmax, cfg, update=1, seed=4):
     lat.setup_mg(W, ntv, setup_iters=3, smooth=3)
     t0 = lat.pack(dev(random_spinors(dims, 1, seed_for(cfg, "x") + seed)))
     X = lat.field(nev)
-    prm = qmg.default_eig_params(m_min=mmin, m_max=mmax, maxiter=3000, update_interp=update)
+    prm = qmg.default_eig_params(m_min=mmin, m_max=mmax, maxiter=3000, update_interp=update, block=nblk)
     st, lam, stats = lat.eigensolve(nev, X, t0, V0=W, n0=ntv, params=prm)
     return qmg, lat, U, st, lam, host(lat.unpack(X, nev)), stats
 
@@ -35,30 +35,33 @@ def _check_pairs(U, m0, lam, X, tol):
     assert np.allclose(G, np.eye(k), atol=1e-9)
 
 
-def test_eigensolve_4x4_matches_dense_oracle():
+@pytest.mark.parametrize("nblk", [1, 4])
+def test_eigensolve_4x4_matches_dense_oracle(nblk):
     """4^4 lattice, 2^4 blocks, clover, 8 test vectors: the locked eigenvalues are
-    the oracle's smallest-modulus ones, with a restart (m_max = 20) on the way."""
-    case("eigensolve 4^4 vs dense oracle")
+    the oracle's smallest-modulus ones, with restarts (m_max = 20) on the way;
+    one target per step and four targets solved as one multi-shift batch."""
+    case("eigensolve 4^4 vs dense oracle, block %d" % nblk)
     dims, m0 = (4, 4, 4, 4), -0.5
     U = random_links(dims, 0.5, seed_for(9, "U"))
     ref, _ = eigen.smallest_eigenpairs(U, m0, oclover.clover_term(U, 1.0), 40)
     # pick nev at a clear gap in |lambda| so "the nev smallest" is unambiguous
     gaps = np.diff(np.abs(ref))
     nev = 10 + int(np.argmax(gaps[9:20] > 1e-3))
-    qmg, lat, U2, st, lam, X, stats = _run(dims, (2, 2, 2, 2), m0, 8, nev, 10, 20, 9)
+    qmg, lat, U2, st, lam, X, stats = _run(dims, (2, 2, 2, 2), m0, 8, nev, 10, 20, 9, nblk=nblk)
     assert st == 0 and stats["converged"] == nev, stats
     assert np.allclose(np.sort(lam), np.sort(ref[:nev]), atol=1e-9, rtol=0)
     _check_pairs(U, m0, lam, X, 1.1e-8)
     assert stats["interp_updates"] >= 1
 
 
-def test_eigensolve_8x4_pairs_valid():
+@pytest.mark.parametrize("nblk", [1, 8])
+def test_eigensolve_8x4_pairs_valid(nblk):
     """8^4 lattice, 4^4 blocks (the 4^4-block kernels), 4 test vectors so the
     interpolation is rebuilt from eigenvectors: every locked pair has residual
     <= 1e-8 under the oracle's operator and the vectors are orthonormal."""
-    case("eigensolve 8^4 pairs")
+    case("eigensolve 8^4 pairs, block %d" % nblk)
     dims, m0 = (8, 8, 8, 8), -0.5
-    qmg, lat, U, st, lam, X, stats = _run(dims, (4, 4, 4, 4), m0, 4, 8, 10, 16, 10)
+    qmg, lat, U, st, lam, X, stats = _run(dims, (4, 4, 4, 4), m0, 4, 8, 10, 20, 10, nblk=nblk)
     assert st == 0 and stats["converged"] == 8, stats
     _check_pairs(U, m0, lam, X, 1.1e-8)
     assert stats["interp_updates"] >= 1
@@ -74,6 +77,9 @@ def test_eigensolve_bad_arguments():
     t0 = lat.field(1)
     with pytest.raises(qmg.QmgError) as e:
         lat.eigensolve(2, X, t0, params=qmg.default_eig_params(m_min=10, m_max=10))
+    assert e.value.status == -1
+    with pytest.raises(qmg.QmgError) as e:
+        lat.eigensolve(2, X, t0, params=qmg.default_eig_params(m_min=10, m_max=20, block=11))
     assert e.value.status == -1
     with pytest.raises(qmg.QmgError) as e:
         lat.eigensolve(0, X, t0)
