@@ -16,7 +16,8 @@ constexpr int64_t kChunk = (int64_t)kDotWG * kDotPerThread;
 template <typename S>
 __global__ __launch_bounds__(kDotWG) void k_dot_stage1(double* partial, const typename PT<S>::stor* V, int64_t vstride,
                                                       int J, const typename PT<S>::stor* w, int64_t n,
-                                                      int64_t stride, int nchunk, int with_self) {
+                                                      int64_t stride, int nchunk, int with_self,
+                                                      int64_t vkstride) {
   __shared__ double red[2 * (kDotWG / 64)];
   const int chunk = blockIdx.x, k = blockIdx.y;
   const int64_t i0 = chunk * kChunk + threadIdx.x;
@@ -28,7 +29,7 @@ __global__ __launch_bounds__(kDotWG) void k_dot_stage1(double* partial, const ty
     wl[t] = i < n ? ldcv<double>(wk, i) : czero<double>();
   }
   for (int j = 0; j < J; ++j) {
-    const auto* vj = V + j * vstride + k * stride;
+    const auto* vj = V + j * vstride + k * vkstride;
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < kDotPerThread; ++t) {
@@ -187,9 +188,24 @@ hipError_t launch_multidot(int p, double* dots, const void* V, int64_t vstride, 
     using S = decltype(tag);
     using P = typename PT<S>::stor;
     hipLaunchKernelGGL(k_dot_stage1<S>, dim3(nchunk, nrhs), dim3(kDotWG), 0, s, partial, (const P*)V, vstride, J,
-                       (const P*)w, n, stride, nchunk, with_self);
+                       (const P*)w, n, stride, nchunk, with_self, stride);
   });
   hipLaunchKernelGGL(k_dot_stage2, dim3(J + with_self, nrhs), dim3(256), 0, s, dots, partial, J + with_self, nchunk);
+  return hipGetLastError();
+}
+
+// dots[(k*J + j)*2] = <V_j, w_k> for nw vectors w_k (offset k*wstride) against
+// one shared basis: the work-groups of all w_k read a basis chunk together
+hipError_t launch_multidot_shared(int p, double* dots, const void* V, int64_t vstride, int J, const void* w,
+                                  int64_t wstride, int nw, int64_t n, double* partial, hipStream_t s) {
+  const int nchunk = (int)((n + kChunk - 1) / kChunk);
+  by_prec(p, [&](auto tag) {
+    using S = decltype(tag);
+    using P = typename PT<S>::stor;
+    hipLaunchKernelGGL(k_dot_stage1<S>, dim3(nchunk, nw), dim3(kDotWG), 0, s, partial, (const P*)V, vstride, J,
+                       (const P*)w, n, wstride, nchunk, 0, (int64_t)0);
+  });
+  hipLaunchKernelGGL(k_dot_stage2, dim3(J, nw), dim3(256), 0, s, dots, partial, J, nchunk);
   return hipGetLastError();
 }
 

@@ -177,12 +177,12 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
   void* QU = ws_get(c, "eg_Qu", fb * nblk);
   void* R = ws_get(c, "eg_r", fb * nblk);
   const int nmax = std::max(std::max(mmax, nev), c->ntv) + 2;
-  double* d_dots = (double*)ws_get(c, "eg_dots", sizeof(double) * 2 * nmax);
-  double* d_part = (double*)ws_get(c, "eg_part", sizeof(double) * multidot_partial_doubles(n, nmax, 1));
+  double* d_dots = (double*)ws_get(c, "eg_dots", sizeof(double) * 4 * nmax);
+  double* d_part = (double*)ws_get(c, "eg_part", sizeof(double) * multidot_partial_doubles(n, nmax, 2));
   double* d_coef = (double*)ws_get(c, "eg_coef", sizeof(double) * 2 * nmax);
   if (!V || !W || !T || !Tc || !U || !QU || !R || !d_dots || !d_part || !d_coef)
     return set_err(c, QMG_E_NOMEM, "out of device memory (eigensolver)");
-  std::vector<double> hbuf(2 * nmax);
+  std::vector<double> hbuf(4 * nmax);
   const double zero_tau = 0.0;
 
   // ---- field helpers (one field, FP64)
@@ -227,27 +227,33 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
     hipError_t e = hipMemcpyAsync(dst, src, fb, hipMemcpyDeviceToDevice, s);
     return e == hipSuccess ? QMG_OK : hip_err(c, e, "eigensolver copy");
   };
-  // x <- x - X X^H x - B B^H x (two classical Gram-Schmidt passes); returns ||x||
+  // x <- x - X X^H x - B B^H x by classical Gram-Schmidt; a second pass only
+  // when the first removed more than half of ||x||^2 (DGKS test, the norm
+  // before the pass following from the projections); returns ||x||
   int nconv = 0, m = 0;
   auto orth = [&](void* x, const void* B, int nb, double& nrm) -> qmg_status {
     std::vector<cd> d;
     for (int pass = 0; pass < 2; ++pass) {
+      double removed = 0;
       if (nconv > 0) {
         qmg_status st = dots(X, nconv, x, d);
         if (st != QMG_OK) return st;
-        for (cd& v : d) v = -v;
+        for (cd& v : d) { removed += std::norm(v); v = -v; }
         st = axpy(x, X, nconv, d);
         if (st != QMG_OK) return st;
       }
       if (nb > 0) {
         qmg_status st = dots(B, nb, x, d);
         if (st != QMG_OK) return st;
-        for (cd& v : d) v = -v;
+        for (cd& v : d) { removed += std::norm(v); v = -v; }
         st = axpy(x, B, nb, d);
         if (st != QMG_OK) return st;
       }
+      qmg_status st = norm(x, nrm);
+      if (st != QMG_OK) return st;
+      if (nrm * nrm >= 0.5 * (nrm * nrm + removed)) break;
     }
-    return norm(x, nrm);
+    return QMG_OK;
   };
   // small matrices (column-major, leading dimension mmax + 1)
   const int ld = mmax + 1;
@@ -258,10 +264,18 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
   auto append = [&](const void* src, double nrm) -> qmg_status {
     qmg_status st = scale(fld(V, m), src, cd(1.0 / nrm));
     if (st == QMG_OK) st = applyQ(fld(W, m), fld(V, m));
-    std::vector<cd> gw, mv;
-    if (st == QMG_OK) st = dots(W, m + 1, fld(W, m), gw);
-    if (st == QMG_OK) st = dots(W, m + 1, fld(V, m), mv);
     if (st != QMG_OK) return st;
+    // the new columns W^H w_m and W^H v_m in one pass over W
+    const int64_t wstride = ((char*)fld(V, m) - (char*)fld(W, m)) / 16;
+    hipError_t e = launch_multidot_shared(QMG_F64, d_dots, W, n, m + 1, fld(W, m), wstride, 2, n, d_part, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hbuf.data(), d_dots, sizeof(double) * 4 * (m + 1), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(c, e, "eigensolver dots");
+    std::vector<cd> gw(m + 1), mv(m + 1);
+    for (int i = 0; i <= m; ++i) {
+      gw[i] = cd(hbuf[2 * i], hbuf[2 * i + 1]);
+      mv[i] = cd(hbuf[2 * (m + 1 + i)], hbuf[2 * (m + 1 + i) + 1]);
+    }
     for (int i = 0; i <= m; ++i) {
       G[(size_t)m * ld + i] = gw[i];
       G[(size_t)i * ld + m] = std::conj(gw[i]);
@@ -401,8 +415,31 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
       rns.assign(cand.size(), 0.0);
       bool relock = false;
       for (size_t i = 0; i < cand.size(); ++i) {
-        st = ritz(S[cand[i]], th[cand[i]], fld(U, (int)i), fld(QU, (int)i), fld(R, (int)i), rns[i]);
-        if (st != QMG_OK) return st;
+        // ||r||^2 = s^H G s - 2 theta Re(s^H M s) + theta^2 (V orthonormal, ||s|| = 1);
+        // far from convergence only r = (W - theta V) s is formed
+        const std::vector<cd>& sv = S[cand[i]];
+        const double thi = th[cand[i]];
+        cd sgs = 0, sms = 0;
+        for (int b = 0; b < m; ++b)
+          for (int a = 0; a < m; ++a) {
+            sgs += std::conj(sv[a]) * G[(size_t)b * ld + a] * sv[b];
+            sms += std::conj(sv[a]) * M[(size_t)b * ld + a] * sv[b];
+          }
+        const double est = std::sqrt(std::max(0.0, sgs.real() - 2.0 * thi * sms.real() + thi * thi));
+        if (est > 100.0 * prm->tol) {
+          void* ri = fld(R, (int)i);
+          hipError_t e = launch_fill_zero(ri, fb, s);
+          if (e != hipSuccess) return hip_err(c, e, "eigensolver zero");
+          std::vector<cd> ms(m);
+          for (int a = 0; a < m; ++a) ms[a] = -thi * sv[a];
+          st = axpy(ri, W, m, sv);
+          if (st == QMG_OK) st = axpy(ri, V, m, ms);
+          if (st != QMG_OK) return st;
+          rns[i] = est;
+        } else {
+          st = ritz(sv, thi, fld(U, (int)i), fld(QU, (int)i), fld(R, (int)i), rns[i]);
+          if (st != QMG_OK) return st;
+        }
         // with nev pairs locked, go on only while the first target lies below
         // the largest locked |lambda| by more than its residual (greedy
         // locking can take a slightly larger pair first); a pair that then

@@ -135,6 +135,8 @@ hipError_t launch_scale(int p, void* y, const void* x, const double* a, int64_t 
 hipError_t launch_xmy(int p, void* y, const void* x, int64_t n, int64_t stride, int nrhs, hipStream_t s);
 hipError_t launch_gamma5_bs(int p, void* y, const void* x, int64_t n, int bs_log, hipStream_t s);
 size_t multidot_partial_doubles(int64_t n, int J, int nrhs);
+hipError_t launch_multidot_shared(int p, double* dots, const void* V, int64_t vstride, int J, const void* w,
+                                  int64_t wstride, int nw, int64_t n, double* partial, hipStream_t s);
 hipError_t launch_fill_zero(void* y, size_t bytes, hipStream_t s);
 // ---- force.hip
 hipError_t launch_unit_coarse(void* y, int nb, int nc, int col, hipStream_t s);
