@@ -189,6 +189,13 @@ qmg_status qmg_solve_shifted(qmg_ctx* ctx, void* x, const void* b, const double*
 qmg_status qmg_gauge_force(qmg_ctx* ctx, double* dU, double* dUbar, const void* phi,
                            const void* x, hipStream_t stream);
 
+/* Local coherence measure lc(v_k) = ||Pi v_k|| / ||v_k|| (Sec. 3.1), Pi the
+ * orthogonal projection on the range of the current interpolation P; v:
+ * nrhs internal F64 fields; lc: host array [nrhs].  Since P has orthonormal
+ * columns per aggregate, ||Pi v|| = ||P^H v||.  Needs qmg_set_test_vectors or
+ * qmg_setup_mg; synchronises the stream. */
+qmg_status qmg_local_coherence(qmg_ctx* ctx, double* lc, const void* v, int nrhs, hipStream_t stream);
+
 /* ---- GD-lambdaAMG eigensolver (Alg. GD-lambdaAMG, Sec. 3.3; defaults from
  * the paper's parameter table, see qmg_default_eig_params). */
 typedef struct {

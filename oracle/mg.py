@@ -85,6 +85,14 @@ def prolong(P, y, dims, block):
     return from_aggregates(a, dims, block)
 
 
+def local_coherence(P, psi, block):
+    """lc(v) = ||Pi v|| / ||v|| with Pi = P P^H the orthogonal projection on the
+    range of P (Sec. 3.1, local coherence measure); P's columns are
+    orthonormal per aggregate, so Pi v = prolong(restrict(v))."""
+    dims = psi.shape[:4]
+    return np.linalg.norm(prolong(P, restrict(P, psi, block), dims, block)) / np.linalg.norm(psi)
+
+
 def gamma5_coarse(y):
     ntv = y.shape[-1] // 2
     s = np.concatenate([np.ones(ntv), -np.ones(ntv)])

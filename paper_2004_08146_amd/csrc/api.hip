@@ -529,6 +529,37 @@ qmg_status qmg_gauge_force(qmg_ctx* c, double* dU, double* dUbar, const void* ph
   return hipchk(c, launch_force(c, dU, dUbar, phi, x, s), "gauge_force");
 }
 
+qmg_status qmg_local_coherence(qmg_ctx* c, double* lc, const void* v, int nrhs, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_mg(c));
+  if (!lc || !v) return set_err(c, QMG_E_ARG, "local_coherence: null pointer");
+  hipSetDevice(c->device);
+  const int64_t nf = (int64_t)field_elems(c), ncs = (int64_t)coarse_elems(c);
+  void* y = ws_get(c, "lc_y", (size_t)ncs * nrhs * 16);
+  double* d = (double*)ws_get(c, "lc_d", sizeof(double) * 4 * nrhs);
+  double* part = (double*)ws_get(c, "lc_part",
+                                 sizeof(double) * std::max(multidot_partial_doubles(nf, 1, nrhs),
+                                                           multidot_partial_doubles(ncs, 1, nrhs)));
+  if (!y || !d || !part) return set_err(c, QMG_E_NOMEM, "out of device memory (local coherence)");
+  hipError_t e = launch_restrict(c, QMG_F64, y, v, nrhs, s);
+  // ||P^H v_k||^2 and ||v_k||^2 (squared norms as self dot products)
+  if (e == hipSuccess) e = launch_multidot(QMG_F64, d, y, 0, 1, y, ncs, ncs, nrhs, part, s, 0);
+  std::vector<double> hy(2 * nrhs), hv(2 * nrhs);
+  if (e == hipSuccess) e = hipMemcpyAsync(hy.data(), d, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = launch_multidot(QMG_F64, d, v, 0, 1, v, nf, nf, nrhs, part, s, 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(hv.data(), d, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c, e, "local coherence");
+  for (int k = 0; k < nrhs; ++k) {
+    if (!(hv[2 * k] > 0) || !std::isfinite(hv[2 * k]) || !std::isfinite(hy[2 * k]))
+      return set_err(c, QMG_E_NUMERIC, "local coherence of a zero or non-finite vector");
+    lc[k] = std::sqrt(std::max(0.0, hy[2 * k]) / hv[2 * k]);
+  }
+  return QMG_OK;
+}
+
 qmg_status qmg_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const void* V0, int n0, const void* t0,
                           const qmg_eig_params* prm, qmg_eig_stats* st, hipStream_t s) {
   if (!c) return QMG_E_ARG;

@@ -90,6 +90,7 @@ _SIG = {
     "qmg_solve_shifted": ([_vp, _vp, _vp, _dp, _i, ctypes.POINTER(Params), ctypes.POINTER(Stats), _vp], _i),
     "qmg_gauge_force": ([_vp, _vp, _vp, _vp, _vp, _vp], _i),
     "qmg_autotune": ([_vp, ctypes.c_char_p], _i),
+    "qmg_local_coherence": ([_vp, _dp, _vp, _i, _vp], _i),
     "qmg_default_eig_params": ([], EigParams),
     "qmg_eigensolve": ([_vp, _i, _dp, _vp, _vp, _i, _vp, ctypes.POINTER(EigParams), ctypes.POINTER(EigStats),
                         _vp], _i),
@@ -305,6 +306,14 @@ class Lattice:
         self._check(_lib.qmg_gauge_force(self._h, _ptr(G), _ptr(Gb), _ptr(phi), _ptr(x), _stream()),
                     "gauge_force")
         return G, Gb
+
+    def local_coherence(self, v, nrhs=1):
+        """lc(v_k) = ||Pi v_k|| / ||v_k|| for nrhs internal F64 fields (numpy array)."""
+        import numpy as np
+        lc = np.zeros(nrhs)
+        self._check(_lib.qmg_local_coherence(self._h, lc.ctypes.data_as(_dp), _ptr(v), nrhs, _stream()),
+                    "local_coherence")
+        return lc
 
     def eigensolve(self, nev, X, t0, V0=None, n0=0, params=None):
         """GD-lambdaAMG: returns (status, eigenvalues (numpy, lock order), stats dict);

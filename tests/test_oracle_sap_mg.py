@@ -314,3 +314,35 @@ def test_shifted_solve_matches_dense():
         assert np.linalg.norm(x.reshape(-1) - xs) <= kappa * 1e-10 * np.linalg.norm(xs)
         its.append(it)
     assert its[1] < its[0] / 2
+
+
+def test_local_coherence_pins():
+    """lc(v) = ||Pi v|| / ||v|| (Sec. 3.1): 1 on the test vectors, <= 1 always, the
+    dense projector P P^H gives the same values, and for Gaussian vectors the
+    mean of lc^2 is rank(P) / N (0.25 for 4^4 with 2^4 aggregates and 24 test
+    vectors, the no-coherence value the paper quotes)."""
+    from oracle import mg
+    from synth import random_spinors
+    dims, block, ntv = (4, 4, 4, 4), (2, 2, 2, 2), 24
+    W = random_spinors(dims, ntv, 3)
+    P = mg.build_P(W, block)
+    for w in W[:4]:
+        assert abs(mg.local_coherence(P, w, block) - 1.0) < 1e-12
+    V = random_spinors(dims, 64, 5)
+    lc = np.array([mg.local_coherence(P, v, block) for v in V])
+    assert np.all(lc <= 1.0 + 1e-12)
+    N = V[0].size
+    assert abs(np.mean(lc ** 2) - 768 / 3072) < 0.01
+    # dense projector from the prolongations of the coarse unit vectors
+    nb = np.prod([d // b for d, b in zip(dims, block)])
+    cols = []
+    for i in range(nb * 2 * ntv):
+        y = np.zeros(nb * 2 * ntv, dtype=np.complex128)
+        y[i] = 1.0
+        cols.append(mg.prolong(P, y.reshape(nb, 2 * ntv), dims, block).ravel())
+    Pd = np.array(cols).T
+    assert np.allclose(Pd.conj().T @ Pd, np.eye(Pd.shape[1]), atol=1e-12)
+    for v, l in zip(V[:8], lc[:8]):
+        x = v.ravel()
+        assert abs(np.linalg.norm(Pd @ (Pd.conj().T @ x)) / np.linalg.norm(x) - l) < 1e-12
+    assert N == Pd.shape[0]
