@@ -125,11 +125,14 @@ class Coarse:
         self.Dc = Dc
         self.nbr = nbr
 
-    def apply(self, y, tau):
+    def apply(self, y, tau, qform=False):
+        """A_c(tau) y; with qform Gamma5^c A_c(tau) y = (Gamma5^c D_c - tau) y, the
+        Galerkin projection P^H (Q - tau) P (Gamma5 P = P Gamma5^c)."""
         out = np.einsum("bij,bj->bi", self.Dc[:, 0], y)
         for d in range(1, 9):
             out = out + np.einsum("bij,bj->bi", self.Dc[:, d], y[self.nbr[:, d]])
-        return out - tau * gamma5_coarse(y)
+        out = out - tau * gamma5_coarse(y)
+        return gamma5_coarse(out) if qform else out
 
 
 class TwoLevel:
@@ -143,13 +146,14 @@ class TwoLevel:
         self.coarse = Coarse(coarse_operator(op, self.P, block),
                              bl.neighbour_table(op.dims, block))
 
-    def vcycle(self, r, tau, nu, n_mr, coarse_iters, coarse_tol=None):
-        """z = nu SAP sweeps on A_tau z = r started from P A_c^{-1}(approx) P^H r."""
+    def vcycle(self, r, tau, nu, n_mr, coarse_iters, coarse_tol=None, qform=False):
+        """z = nu SAP sweeps on A_tau z = r started from P A_c^{-1}(approx) P^H r
+        (qform: the same cycle for Q - tau, coarse operator Gamma5^c A_c)."""
         rc = restrict(self.P, r, self.block)
-        yc = gmres(lambda v: self.coarse.apply(v, tau), rc, coarse_iters, coarse_tol)[0]
+        yc = gmres(lambda v: self.coarse.apply(v, tau, qform), rc, coarse_iters, coarse_tol)[0]
         z = prolong(self.P, yc, self.op.dims, self.block)
         if nu > 0:
-            z = sap(self.op, r, z, tau, self.block, nu, n_mr)
+            z = sap(self.op, r, z, tau, self.block, nu, n_mr, qform)
         return z
 
 

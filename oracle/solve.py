@@ -12,17 +12,20 @@ from .sap import sap
 
 
 def solve_shifted(op, b, tau, block, mg=None, tol=1e-10, restart=8, maxiter=500,
-                  nu=3, n_mr=3, coarse_iters=50, coarse_tol=0.5):
-    f = gamma5(b)
+                  nu=3, n_mr=3, coarse_iters=50, coarse_tol=0.5, qform=False):
+    """qform: solve (Q - tau) x = b directly, every level built on Q - tau (the
+    comparison of Sec. 3.3) instead of the Gamma5-preconditioned form."""
+    f = b.copy() if qform else gamma5(b)
 
     def A(v):
-        return op.A(v, tau)
+        av = op.A(v, tau)
+        return gamma5(av) if qform else av
 
     if mg is not None:
         def M(v):
-            return mg.vcycle(v, tau, nu, n_mr, coarse_iters, coarse_tol)
+            return mg.vcycle(v, tau, nu, n_mr, coarse_iters, coarse_tol, qform)
     else:
         def M(v):
-            return sap(op, v, 0.0 * v, tau, block, nu, n_mr)
+            return sap(op, v, 0.0 * v, tau, block, nu, n_mr, qform)
 
     return fgmres(A, M, f, tol, restart, maxiter)
