@@ -81,6 +81,9 @@ typedef struct {
   qmg_prec mg_prec;    /* precision of the V-cycle (SAP, transfer, coarse) */
   int use_coarse;      /* 1: two-level V-cycle; 0: SAP only (no coarse level) */
   int use_graph;       /* 1: replay the V-cycle as a captured HIP graph */
+  int q_form;          /* 0: the Gamma5-preconditioned form (D - tau Gamma5) x = Gamma5 b, every
+                          level built on D - tau Gamma5 (eq. (3.7), the default); 1: FGMRES,
+                          SAP and the coarse grid on Q - tau itself (the comparison of Sec. 3.3) */
 } qmg_params;
 
 typedef struct {

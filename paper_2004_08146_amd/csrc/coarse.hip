@@ -54,6 +54,7 @@ __global__ __launch_bounds__(256) void k_split(Geom g, double2* out9, const doub
 
 struct TauArr {
   double t[QMG_MAXRHS];
+  int qform;  // 1: Gamma5^c (D_c - tau Gamma5^c) = Gamma5^c D_c - tau, the Galerkin P^H (Q - tau) P
 };
 
 template <typename S, typename C, int T>
@@ -85,7 +86,10 @@ __global__ __launch_bounds__(64) void k_coarse_apply(Geom g, typename PT<C>::sto
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int k = k0 + t;
-    if (k < nrhs) stcv(out, ((int64_t)k * g.nb + b) * nc + i, acc[t] - (R(tau.t[k]) * g5) * xin[0][t][i]);
+    if (k < nrhs) {
+      const cpx<R> v = acc[t] - (R(tau.t[k]) * g5) * xin[0][t][i];
+      stcv(out, ((int64_t)k * g.nb + b) * nc + i, tau.qform ? g5 * v : v);
+    }
   }
 }
 
@@ -153,7 +157,8 @@ __global__ __launch_bounds__(64 * NT) void k_coarse_mfma(Geom g, typename PT<C>:
     const int i = 16 * t + mrow<R>(l, r);
     const R g5 = i < NC / 2 ? R(1) : R(-1);
     const cpx<R> self = Bself[i][ln];
-    const cpx<R> v = {acc_re[r] - tn * g5 * self.re, acc_im[r] - tn * g5 * self.im};
+    cpx<R> v = {acc_re[r] - tn * g5 * self.re, acc_im[r] - tn * g5 * self.im};
+    if (tau.qform) v = g5 * v;
     stcv(out, ((int64_t)n * g.nb + b) * NC + i, v);
   }
 }
@@ -179,10 +184,12 @@ void capply_mfma(const qmg_ctx* c, int p, void* out, const void* in, const TauAr
 }
 
 template <typename S, int T>
-void capply_t(const qmg_ctx* c, int p, void* out, const void* in, const double* htau, int nrhs, hipStream_t s) {
+void capply_t(const qmg_ctx* c, int p, void* out, const void* in, const double* htau, int nrhs, hipStream_t s,
+              int qform) {
   using P = typename PT<S>::stor;
   TauArr dtau;
   for (int i = 0; i < QMG_MAXRHS; ++i) dtau.t[i] = i < nrhs ? htau[i] : 0.0;
+  dtau.qform = qform;
   const int nc = 2 * c->ntv;
   dim3 grid(c->g.nb, (nrhs + T - 1) / T);
   if (p == QMG_F64)
@@ -194,12 +201,14 @@ void capply_t(const qmg_ctx* c, int p, void* out, const void* in, const double* 
 }
 
 template <typename S>
-void capply_s(const qmg_ctx* c, int p, void* out, const void* in, const double* dtau, int nrhs, hipStream_t s) {
+void capply_s(const qmg_ctx* c, int p, void* out, const void* in, const double* dtau, int nrhs, hipStream_t s,
+              int qform) {
   // MFMA path when the coarse dimension is a multiple of 16 (ntv = 8, 16, 24) and
   // enough right-hand sides share each matrix block
   if (c->tune.coarse_mfma && (2 * c->ntv) % 16 == 0 && 2 * c->ntv <= 48 && nrhs >= c->tune.coarse_mfma_min_rhs) {
     TauArr t;
     for (int i = 0; i < QMG_MAXRHS; ++i) t.t[i] = i < nrhs ? dtau[i] : 0.0;
+    t.qform = qform;
     if constexpr (std::is_same<S, double>::value) {
       if (p == QMG_F64) { capply_mfma<S>(c, p, out, in, t, nrhs, s); return; }
     } else {
@@ -207,9 +216,9 @@ void capply_s(const qmg_ctx* c, int p, void* out, const void* in, const double* 
       return;
     }
   }
-  if (nrhs >= 4) capply_t<S, 4>(c, p, out, in, dtau, nrhs, s);
-  else if (nrhs == 2) capply_t<S, 2>(c, p, out, in, dtau, nrhs, s);
-  else capply_t<S, 1>(c, p, out, in, dtau, nrhs, s);
+  if (nrhs >= 4) capply_t<S, 4>(c, p, out, in, dtau, nrhs, s, qform);
+  else if (nrhs == 2) capply_t<S, 2>(c, p, out, in, dtau, nrhs, s, qform);
+  else capply_t<S, 1>(c, p, out, in, dtau, nrhs, s, qform);
 }
 
 }  // namespace
@@ -223,9 +232,9 @@ hipError_t launch_split_stencil(const qmg_ctx* c, void* out9, const void* in, hi
 
 // tau: host array of nrhs shifts
 hipError_t launch_coarse_apply(const qmg_ctx* c, int p, void* out, const void* in, const double* dtau, int nrhs,
-                               hipStream_t s) {
-  if (p == QMG_F64) capply_s<double>(c, p, out, in, dtau, nrhs, s);
-  else if (p == QMG_F32) capply_s<float>(c, p, out, in, dtau, nrhs, s);
-  else capply_s<bf16_t>(c, p, out, in, dtau, nrhs, s);
+                               hipStream_t s, int qform) {
+  if (p == QMG_F64) capply_s<double>(c, p, out, in, dtau, nrhs, s, qform);
+  else if (p == QMG_F32) capply_s<float>(c, p, out, in, dtau, nrhs, s, qform);
+  else capply_s<bf16_t>(c, p, out, in, dtau, nrhs, s, qform);
   return hipGetLastError();
 }

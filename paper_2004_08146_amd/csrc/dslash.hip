@@ -315,14 +315,19 @@ hipError_t launch_dslash(const qmg_ctx* c, int p, void* out, const void* in, con
 }
 
 hipError_t launch_dslash_d_in(const qmg_ctx* c, void* out, const void* in, int in_prec, const double* tau,
-                              int nrhs, hipStream_t s) {
-  if (in_prec == QMG_F64) return launch_dslash(c, QMG_F64, out, in, tau, nrhs, 0, s);
-  if (c->clover) {
-    if (in_prec == QMG_F32) launch_t<double, true, 0, float>(c, out, in, tau, nrhs, s, QMG_F64);
-    else launch_t<double, true, 0, bf16_t>(c, out, in, tau, nrhs, s, QMG_F64);
-  } else {
-    if (in_prec == QMG_F32) launch_t<double, false, 0, float>(c, out, in, tau, nrhs, s, QMG_F64);
-    else launch_t<double, false, 0, bf16_t>(c, out, in, tau, nrhs, s, QMG_F64);
-  }
+                              int nrhs, hipStream_t s, int mode) {
+  if (in_prec == QMG_F64) return launch_dslash(c, QMG_F64, out, in, tau, nrhs, mode, s);
+  auto go = [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    if (c->clover) {
+      if (in_prec == QMG_F32) launch_t<double, true, M, float>(c, out, in, tau, nrhs, s, QMG_F64);
+      else launch_t<double, true, M, bf16_t>(c, out, in, tau, nrhs, s, QMG_F64);
+    } else {
+      if (in_prec == QMG_F32) launch_t<double, false, M, float>(c, out, in, tau, nrhs, s, QMG_F64);
+      else launch_t<double, false, M, bf16_t>(c, out, in, tau, nrhs, s, QMG_F64);
+    }
+  };
+  if (mode == 0) go(std::integral_constant<int, 0>{});
+  else go(std::integral_constant<int, 1>{});
   return hipGetLastError();
 }

@@ -110,7 +110,7 @@ __global__ void k_gm_solve(GmState st, double* coef, int kk, int nrhs) {
 // Fixed-step coarse GMRES with every scalar on the device (graph-capturable).
 // Work buffers come from ws (allocate them before a capture with the same sizes).
 qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
-                               hipStream_t s) {
+                               hipStream_t s, int qform) {
   const int cp = coarse_prec(p);
   const int64_t n = (int64_t)coarse_elems(c);
   const size_t vb = (size_t)n * cbytes(cp);
@@ -141,7 +141,7 @@ qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const 
   }
   for (int j = 0; j < m && e == hipSuccess; ++j) {
     char* Vj = (char*)V + (size_t)j * bb;
-    e = launch_coarse_apply(c, p, w, Vj, tau, nrhs, s);
+    e = launch_coarse_apply(c, p, w, Vj, tau, nrhs, s, qform);
     for (int pass = 0; pass < 1 && e == hipSuccess; ++pass) {
       e = launch_multidot(cp, dots, V, vs, j + 1, w, n, n, nrhs, part, s, 0);
       if (e == hipSuccess) {

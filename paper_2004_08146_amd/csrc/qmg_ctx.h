@@ -100,10 +100,11 @@ hipError_t launch_dslash(const qmg_ctx* c, int p, void* out, const void* in, con
                          int nrhs, int mode, hipStream_t s);
 // (D - tau Gamma5) in FP64 arithmetic and storage, reading an input field stored in in_prec
 hipError_t launch_dslash_d_in(const qmg_ctx* c, void* out, const void* in, int in_prec, const double* tau,
-                              int nrhs, hipStream_t s);
+                              int nrhs, hipStream_t s, int mode = 0);
 // ---- sap.hip
+// qform: SAP for Q - tau = Gamma5 A_tau itself instead of A_tau
 hipError_t launch_sap_colour(const qmg_ctx* c, int p, void* x, const void* f, const double* tau,
-                             int nrhs, int colour, int n_mr, hipStream_t s);
+                             int nrhs, int colour, int n_mr, hipStream_t s, int qform = 0);
 // ---- transfer.hip
 hipError_t launch_build_P(const qmg_ctx* c, void* P64, const void* W, int ntv, int* d_fail,
                           hipStream_t s);
@@ -114,7 +115,7 @@ hipError_t launch_split_stencil(const qmg_ctx* c, void* out9, const void* in, hi
 hipError_t launch_restrict_into_dc(const qmg_ctx* c, void* Dc64, const void* in9, int col,
                                    hipStream_t s);
 hipError_t launch_coarse_apply(const qmg_ctx* c, int p, void* out, const void* in, const double* tau,
-                               int nrhs, hipStream_t s);  // tau: host array
+                               int nrhs, hipStream_t s, int qform = 0);  // tau: host array
 // ---- blas.hip (vectors of n complex per right-hand side, k-th rhs at offset k*stride)
 // dots[k*J + j] = <V_j,k , w_k> for j < J (V_j at base + j*vstride), FP64 results on device
 hipError_t launch_multidot(int p, double* dots, const void* V, int64_t vstride, int J, const void* w,
@@ -145,9 +146,9 @@ hipError_t launch_force(const qmg_ctx* c, double* dU, double* dUb, const void* p
 
 // ---- solver.hip
 qmg_status solver_coarse_gmres(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs,
-                               int iters, double tol, int* iters_done, hipStream_t s);
+                               int iters, double tol, int* iters_done, hipStream_t s, int qform = 0);
 qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
-                               hipStream_t s);
+                               hipStream_t s, int qform = 0);
 // z = M r; z is written in precision zprec (FP64, or the preconditioner's own precision)
 qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs,
                          const qmg_params* prm, int* coarse_iters, hipStream_t s, int zprec = QMG_F64);

@@ -121,7 +121,9 @@ __device__ __forceinline__ void hop_block(Spinor<R>& acc, const cpx<R>* sh, cons
   }
 }
 
-template <typename S, bool CLOVER>
+// QF: the procedure for Q - tau = Gamma5 A_tau itself (residual and block
+// operator multiplied by Gamma5: lower two spins change sign)
+template <typename S, bool CLOVER, bool QF>
 __global__ __launch_bounds__(256) void k_sap(SapArgs<S> a) {
   using R = typename PT<S>::real;
   extern __shared__ unsigned char smem[];
@@ -163,7 +165,10 @@ __global__ __launch_bounds__(256) void k_sap(SapArgs<S> a) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) rho.s[s][c] = fs.s[s][c] - (d.s[s][c] - R(0.5) * acc.s[s][c]);
+      for (int c = 0; c < 3; ++c) {
+        const cpx<R> ax = d.s[s][c] - R(0.5) * acc.s[s][c];
+        rho.s[s][c] = (QF && s >= 2) ? fs.s[s][c] + ax : fs.s[s][c] - ax;
+      }
   }
 
   Spinor<R> e;
@@ -200,6 +205,7 @@ __global__ __launch_bounds__(256) void k_sap(SapArgs<S> a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         q.s[s][c] = q.s[s][c] - R(0.5) * acc.s[s][c];
+        if (QF && s >= 2) q.s[s][c] = -q.s[s][c];
         cpx<R> t = cmul_conj(q.s[s][c], rho.s[s][c]);
         v[0] += t.re;
         v[1] += t.im;
@@ -377,7 +383,7 @@ __device__ __forceinline__ void slot_sum3(float (&v)[3], float* red, int slot) {
   }
 }
 
-template <typename S, bool CLOVER, int NS>
+template <typename S, bool CLOVER, int NS, bool QF>
 __global__ __launch_bounds__(256 * NS) void k_sap44(SapArgs<S> a) {
   using P = typename PT<S>::stor;
   __shared__ cpx<float> Ul[36 * 256];
@@ -443,7 +449,10 @@ __global__ __launch_bounds__(256 * NS) void k_sap44(SapArgs<S> a) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rho.s[s][c] = fs.s[s][c] - (d.s[s][c] - 0.5f * acc.s[s][c]);
+        for (int c = 0; c < 3; ++c) {
+          const cpx<float> ax = d.s[s][c] - 0.5f * acc.s[s][c];
+          rho.s[s][c] = (QF && s >= 2) ? fs.s[s][c] + ax : fs.s[s][c] - ax;
+        }
     }
 #pragma unroll 1
     for (int it = 0; it < a.n_mr; ++it) {
@@ -476,6 +485,7 @@ __global__ __launch_bounds__(256 * NS) void k_sap44(SapArgs<S> a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           q.s[s][c] = q.s[s][c] - 0.5f * acc.s[s][c];
+          if (QF && s >= 2) q.s[s][c] = -q.s[s][c];
           const cpx<float> t = cmul_conj(q.s[s][c], rho.s[s][c]);
           v[0] += t.re;
           v[1] += t.im;
@@ -507,7 +517,7 @@ __global__ __launch_bounds__(256 * NS) void k_sap44(SapArgs<S> a) {
 
 template <typename S>
 void launch_s(const qmg_ctx* c, int p, void* x, const void* f, const double* tau, int nrhs, int colour,
-              int n_mr, hipStream_t s) {
+              int n_mr, hipStream_t s, bool qf) {
   using P = typename PT<S>::stor;
   using R = typename PT<S>::real;
   SapArgs<S> a;
@@ -530,26 +540,41 @@ void launch_s(const qmg_ctx* c, int p, void* x, const void* f, const double* tau
     if (b44 && c->tune.sap_variant >= 1) {
       dim3 grid((unsigned)a.nblk);
       if (c->tune.sap_variant == 2) {
-        if (c->clover) hipLaunchKernelGGL((k_sap44<S, true, 2>), grid, dim3(512), 0, s, a);
-        else hipLaunchKernelGGL((k_sap44<S, false, 2>), grid, dim3(512), 0, s, a);
+        if (qf) {
+          if (c->clover) hipLaunchKernelGGL((k_sap44<S, true, 2, true>), grid, dim3(512), 0, s, a);
+          else hipLaunchKernelGGL((k_sap44<S, false, 2, true>), grid, dim3(512), 0, s, a);
+        } else {
+          if (c->clover) hipLaunchKernelGGL((k_sap44<S, true, 2, false>), grid, dim3(512), 0, s, a);
+          else hipLaunchKernelGGL((k_sap44<S, false, 2, false>), grid, dim3(512), 0, s, a);
+        }
       } else {
-        if (c->clover) hipLaunchKernelGGL((k_sap44<S, true, 1>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_sap44<S, false, 1>), grid, dim3(256), 0, s, a);
+        if (qf) {
+          if (c->clover) hipLaunchKernelGGL((k_sap44<S, true, 1, true>), grid, dim3(256), 0, s, a);
+          else hipLaunchKernelGGL((k_sap44<S, false, 1, true>), grid, dim3(256), 0, s, a);
+        } else {
+          if (c->clover) hipLaunchKernelGGL((k_sap44<S, true, 1, false>), grid, dim3(256), 0, s, a);
+          else hipLaunchKernelGGL((k_sap44<S, false, 1, false>), grid, dim3(256), 0, s, a);
+        }
       }
       return;
     }
   }
   dim3 grid((unsigned)(a.nblk * nrhs));
-  if (c->clover) hipLaunchKernelGGL((k_sap<S, true>), grid, dim3(bs), lds, s, a);
-  else hipLaunchKernelGGL((k_sap<S, false>), grid, dim3(bs), lds, s, a);
+  if (qf) {
+    if (c->clover) hipLaunchKernelGGL((k_sap<S, true, true>), grid, dim3(bs), lds, s, a);
+    else hipLaunchKernelGGL((k_sap<S, false, true>), grid, dim3(bs), lds, s, a);
+  } else {
+    if (c->clover) hipLaunchKernelGGL((k_sap<S, true, false>), grid, dim3(bs), lds, s, a);
+    else hipLaunchKernelGGL((k_sap<S, false, false>), grid, dim3(bs), lds, s, a);
+  }
 }
 
 }  // namespace
 
 hipError_t launch_sap_colour(const qmg_ctx* c, int p, void* x, const void* f, const double* tau, int nrhs,
-                             int colour, int n_mr, hipStream_t s) {
-  if (p == QMG_F64) launch_s<double>(c, p, x, f, tau, nrhs, colour, n_mr, s);
-  else if (p == QMG_F32) launch_s<float>(c, p, x, f, tau, nrhs, colour, n_mr, s);
-  else launch_s<bf16_t>(c, p, x, f, tau, nrhs, colour, n_mr, s);
+                             int colour, int n_mr, hipStream_t s, int qform) {
+  if (p == QMG_F64) launch_s<double>(c, p, x, f, tau, nrhs, colour, n_mr, s, qform != 0);
+  else if (p == QMG_F32) launch_s<float>(c, p, x, f, tau, nrhs, colour, n_mr, s, qform != 0);
+  else launch_s<bf16_t>(c, p, x, f, tau, nrhs, colour, n_mr, s, qform != 0);
   return hipGetLastError();
 }

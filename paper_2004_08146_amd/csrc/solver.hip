@@ -204,7 +204,7 @@ struct Space {
 
 // ------------------------------------------------------------ coarse GMRES --
 qmg_status solver_coarse_gmres(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
-                               double tol, int* iters_done, hipStream_t s) {
+                               double tol, int* iters_done, hipStream_t s, int qform) {
   const int cp = coarse_prec(p);
   Space sp{c, cp, (int64_t)coarse_elems(c), nrhs, s};
   if (iters < 1) iters = 1;
@@ -228,7 +228,7 @@ qmg_status solver_coarse_gmres(qmg_ctx* c, int p, void* y, const void* r, const 
   std::vector<int> kk(nrhs, 0);
   int done_it = 0;
   for (int j = 0; j < iters; ++j) {
-    hipError_t e = launch_coarse_apply(c, p, w, sp.at(V, j), tau, nrhs, s);
+    hipError_t e = launch_coarse_apply(c, p, w, sp.at(V, j), tau, nrhs, s, qform);
     if (e != hipSuccess) return hip_err(c, e, "coarse apply");
     std::vector<std::vector<cd>> h;
     st = sp.arnoldi(h, V, j, w);
@@ -280,8 +280,8 @@ qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, 
   std::string key;
   {
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%p|%p|%d|%d|%d|%d|%d|%d|%d|", z, r, nrhs, prm->nu_post, prm->n_mr,
-                  prm->coarse_maxiter, (int)prm->mg_prec, prm->use_coarse, zprec);
+    std::snprintf(buf, sizeof(buf), "%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|", z, r, nrhs, prm->nu_post, prm->n_mr,
+                  prm->coarse_maxiter, (int)prm->mg_prec, prm->use_coarse, zprec, prm->q_form);
     key = buf;
     for (int k = 0; k < nrhs; ++k) {
       std::snprintf(buf, sizeof(buf), "%.17g,", tau[k]);
@@ -354,9 +354,9 @@ static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* 
     // a fixed number of coarse steps (graph mode, or coarse_tol <= 0) runs the
     // device-resident GMRES, which never waits for the host
     const bool fixed = graph_safe || !(prm->coarse_tol > 0);
-    qmg_status st = fixed ? coarse_gmres_device(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, s)
+    qmg_status st = fixed ? coarse_gmres_device(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, s, prm->q_form)
                           : solver_coarse_gmres(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, prm->coarse_tol,
-                                                &it, s);
+                                                &it, s, prm->q_form);
     if (st != QMG_OK) return st;
     if (fixed) it = prm->coarse_maxiter;
     if (coarse_iters) *coarse_iters += it;
@@ -368,7 +368,7 @@ static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* 
   }
   for (int sw = 0; sw < prm->nu_post; ++sw)
     for (int col = 0; col < 2; ++col) {
-      e = launch_sap_colour(c, p, zp, rp, tau, nrhs, col, prm->n_mr, s);
+      e = launch_sap_colour(c, p, zp, rp, tau, nrhs, col, prm->n_mr, s, prm->q_form);
       if (e != hipSuccess) return hip_err(c, e, "sap");
     }
   if (p != QMG_F64 && zprec != p) {
@@ -396,7 +396,10 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
   void* f = ws_get(c, "fg_f", bb);
   void* r = ws_get(c, "fg_r", bb);
   if (!V || !Z || !f || !r) return set_err(c, QMG_E_NOMEM, "out of device memory (FGMRES)");
-  hipError_t e = launch_gamma5_bs(QMG_F64, f, b, sp.n * nrhs, c->g.bs_log, s);
+  // Gamma5-preconditioned form: (D - tau Gamma5) x = Gamma5 b; q_form: (Q - tau) x = b itself
+  const int mode = prm->q_form ? 1 : 0;
+  hipError_t e = prm->q_form ? hipMemcpyAsync(f, b, bb, hipMemcpyDeviceToDevice, s)
+                             : launch_gamma5_bs(QMG_F64, f, b, sp.n * nrhs, c->g.bs_log, s);
   if (e == hipSuccess) e = launch_fill_zero(x, bb, s);
   if (e == hipSuccess) e = hipMemcpyAsync(r, f, bb, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return hip_err(c, e, "fgmres init");
@@ -440,7 +443,7 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
       void* w = sp.at(V, j + 1);
       st = solver_vcycle(c, zat(j), sp.at(V, j), tau, nrhs, prm, &ci, s, zprec);
       if (st != QMG_OK) return st;
-      e = launch_dslash_d_in(c, w, zat(j), zprec, tau, nrhs, s);
+      e = launch_dslash_d_in(c, w, zat(j), zprec, tau, nrhs, s, mode);
       if (e != hipSuccess) return hip_err(c, e, "apply");
       std::vector<std::vector<cd>> h;
       st = sp.arnoldi(h, V, j, w, &sig);
@@ -482,7 +485,7 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
       if (st != QMG_OK) return st;
     }
     // true residual r = Gamma5 b - A_tau x
-    e = launch_dslash(c, QMG_F64, r, x, tau, nrhs, 0, s);
+    e = launch_dslash(c, QMG_F64, r, x, tau, nrhs, mode, s);
     if (e == hipSuccess) e = launch_xmy(QMG_F64, r, f, sp.n, sp.n, nrhs, s);
     if (e != hipSuccess) return hip_err(c, e, "residual");
   }
