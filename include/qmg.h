@@ -84,6 +84,8 @@ typedef struct {
   int q_form;          /* 0: the Gamma5-preconditioned form (D - tau Gamma5) x = Gamma5 b, every
                           level built on D - tau Gamma5 (eq. (3.7), the default); 1: FGMRES,
                           SAP and the coarse grid on Q - tau itself (the comparison of Sec. 3.3) */
+  int smoother;        /* 0: red-black SAP (nu_post sweeps); 1: GMRES smoothing, nu_post fixed
+                          GMRES steps on the fine residual equation (Sec. 2's alternative) */
 } qmg_params;
 
 typedef struct {

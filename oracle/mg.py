@@ -22,7 +22,7 @@ Readings where the paper is silent:
 import numpy as np
 
 from . import blocks as bl
-from .dirac import hop_backward, hop_forward
+from .dirac import gamma5, hop_backward, hop_forward
 from .krylov import gmres
 from .sap import block_operator, sap
 
@@ -146,13 +146,20 @@ class TwoLevel:
         self.coarse = Coarse(coarse_operator(op, self.P, block),
                              bl.neighbour_table(op.dims, block))
 
-    def vcycle(self, r, tau, nu, n_mr, coarse_iters, coarse_tol=None, qform=False):
+    def vcycle(self, r, tau, nu, n_mr, coarse_iters, coarse_tol=None, qform=False, smoother="sap"):
         """z = nu SAP sweeps on A_tau z = r started from P A_c^{-1}(approx) P^H r
-        (qform: the same cycle for Q - tau, coarse operator Gamma5^c A_c)."""
+        (qform: the same cycle for Q - tau, coarse operator Gamma5^c A_c).
+        smoother="gmres" (Sec. 2's alternative to SAP): instead of the sweeps,
+        nu steps of GMRES from zero on A e = r - A z, then z + e."""
         rc = restrict(self.P, r, self.block)
         yc = gmres(lambda v: self.coarse.apply(v, tau, qform), rc, coarse_iters, coarse_tol)[0]
         z = prolong(self.P, yc, self.op.dims, self.block)
-        if nu > 0:
+        if nu > 0 and smoother == "gmres":
+            def A(v):
+                av = self.op.A(v, tau)
+                return gamma5(av) if qform else av
+            z = z + gmres(A, r - A(z), nu, None)[0]
+        elif nu > 0:
             z = sap(self.op, r, z, tau, self.block, nu, n_mr, qform)
         return z
 

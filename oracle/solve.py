@@ -12,7 +12,7 @@ from .sap import sap
 
 
 def solve_shifted(op, b, tau, block, mg=None, tol=1e-10, restart=8, maxiter=500,
-                  nu=3, n_mr=3, coarse_iters=50, coarse_tol=0.5, qform=False):
+                  nu=3, n_mr=3, coarse_iters=50, coarse_tol=0.5, qform=False, smoother="sap"):
     """qform: solve (Q - tau) x = b directly, every level built on Q - tau (the
     comparison of Sec. 3.3) instead of the Gamma5-preconditioned form."""
     f = b.copy() if qform else gamma5(b)
@@ -23,7 +23,7 @@ def solve_shifted(op, b, tau, block, mg=None, tol=1e-10, restart=8, maxiter=500,
 
     if mg is not None:
         def M(v):
-            return mg.vcycle(v, tau, nu, n_mr, coarse_iters, coarse_tol, qform)
+            return mg.vcycle(v, tau, nu, n_mr, coarse_iters, coarse_tol, qform, smoother)
     else:
         def M(v):
             return sap(op, v, 0.0 * v, tau, block, nu, n_mr, qform)

@@ -163,6 +163,7 @@ qmg_params qmg_default_params(void) {
   p.use_coarse = 1;
   p.use_graph = 0;
   p.q_form = 0;
+  p.smoother = 0;
   return p;
 }
 
@@ -496,7 +497,7 @@ qmg_status qmg_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int
   QMG_TRY(need_gauge(c));
   QMG_TRY(need_sap(c));
   QMG_TRY(check_tau(c, tau, nrhs));
-  if (!z || !r || z == r || !prm || prm->q_form < 0 || prm->q_form > 1)
+  if (!z || !r || z == r || !prm || prm->q_form < 0 || prm->q_form > 1 || prm->smoother < 0 || prm->smoother > 1)
     return set_err(c, QMG_E_ARG, "vcycle: bad arguments");
   QMG_TRY(check_prec(c, prm->mg_prec));
   if (prm->use_coarse) QMG_TRY(need_mg(c));
@@ -515,7 +516,7 @@ qmg_status qmg_solve_shifted(qmg_ctx* c, void* x, const void* b, const double* t
   qmg_params prm0 = prm ? *prm : qmg_default_params();
   QMG_TRY(check_prec(c, prm0.mg_prec));
   if (!(prm0.tol > 0) || prm0.maxiter < 1 || prm0.restart < 1 || prm0.nu_post < 0 || prm0.n_mr < 0 ||
-      prm0.coarse_maxiter < 1 || prm0.q_form < 0 || prm0.q_form > 1)
+      prm0.coarse_maxiter < 1 || prm0.q_form < 0 || prm0.q_form > 1 || prm0.smoother < 0 || prm0.smoother > 1)
     return set_err(c, QMG_E_ARG, "solve_shifted: bad parameters");
   if (prm0.use_coarse) QMG_TRY(need_mg(c));
   hipSetDevice(c->device);

@@ -260,6 +260,27 @@ hipError_t launch_scale(int p, void* y, const void* x, const double* a, int64_t 
   return hipGetLastError();
 }
 
+template <typename S>
+__global__ __launch_bounds__(256) void k_add(typename PT<S>::stor* y, const typename PT<S>::stor* x, int64_t n,
+                                             int64_t stride) {
+  using R = typename PT<S>::real;
+  const int k = blockIdx.y;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+    const cpx<R> v = ldcv<R>(y + k * stride, i) + ldcv<R>(x + k * stride, i);
+    stcv(y + k * stride, i, v);
+  }
+}
+
+hipError_t launch_add(int p, void* y, const void* x, int64_t n, int64_t stride, int nrhs, hipStream_t s) {
+  by_prec(p, [&](auto tag) {
+    using S = decltype(tag);
+    using P = typename PT<S>::stor;
+    hipLaunchKernelGGL(k_add<S>, dim3(ew_grid(n), nrhs), dim3(256), 0, s, (P*)y, (const P*)x, n, stride);
+  });
+  return hipGetLastError();
+}
+
 hipError_t launch_xmy(int p, void* y, const void* x, int64_t n, int64_t stride, int nrhs, hipStream_t s) {
   by_prec(p, [&](auto tag) {
     using S = decltype(tag);

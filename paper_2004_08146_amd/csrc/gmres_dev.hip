@@ -5,6 +5,8 @@
 // Gram-Schmidt pass per step (no data-dependent second pass).
 // One thread per right-hand side; the rotations follow the same convention as
 // the host solver: [[c, s], [-conj(s), c]] [a; b] = [r; 0], c real.
+#include <string>
+
 #include "qmg_ctx.h"
 
 namespace {
@@ -107,29 +109,32 @@ __global__ void k_gm_solve(GmState st, double* coef, int kk, int nrhs) {
 
 }  // namespace
 
-// Fixed-step coarse GMRES with every scalar on the device (graph-capturable).
+// Fixed-step GMRES from zero with every scalar on the device (graph-capturable),
+// on the coarse operator (fine = false, coarse precision of p) or on the fine
+// stencil in precision p (fine = true; the smoother of Sec. 2's GMRES option).
 // Work buffers come from ws (allocate them before a capture with the same sizes).
-qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
-                               hipStream_t s, int qform) {
-  const int cp = coarse_prec(p);
-  const int64_t n = (int64_t)coarse_elems(c);
+static qmg_status gmres_device(qmg_ctx* c, bool fine, int p, void* y, const void* r, const double* tau, int nrhs,
+                               int iters, hipStream_t s, int qform) {
+  const int cp = fine ? p : coarse_prec(p);
+  const int64_t n = fine ? (int64_t)field_elems(c) : (int64_t)coarse_elems(c);
   const size_t vb = (size_t)n * cbytes(cp);
   const size_t bb = vb * nrhs;
   const int m = iters;
-  void* V = ws_get(c, "cg_V", bb * (m + 1));
-  void* w = ws_get(c, "cg_w", bb);
-  double* dots = (double*)ws_get(c, "gd_dots", sizeof(double) * 2 * (m + 2) * nrhs);
-  double* part = (double*)ws_get(c, "gd_part", sizeof(double) * multidot_partial_doubles(n, m + 2, nrhs));
-  double* coef = (double*)ws_get(c, "gd_coef", sizeof(double) * 2 * (m + 1) * nrhs);
-  double* a = (double*)ws_get(c, "gd_a", sizeof(double) * 2 * nrhs);
-  double* nrm = (double*)ws_get(c, "gd_nrm", sizeof(double) * 2 * nrhs);
+  const std::string tag = fine ? "fd_" : "gd_";
+  void* V = ws_get(c, fine ? "fs_V" : "cg_V", bb * (m + 1));
+  void* w = ws_get(c, fine ? "fs_w" : "cg_w", bb);
+  double* dots = (double*)ws_get(c, tag + "dots", sizeof(double) * 2 * (m + 2) * nrhs);
+  double* part = (double*)ws_get(c, tag + "part", sizeof(double) * multidot_partial_doubles(n, m + 2, nrhs));
+  double* coef = (double*)ws_get(c, tag + "coef", sizeof(double) * 2 * (m + 1) * nrhs);
+  double* a = (double*)ws_get(c, tag + "a", sizeof(double) * 2 * nrhs);
+  double* nrm = (double*)ws_get(c, tag + "nrm", sizeof(double) * 2 * nrhs);
   GmState st;
   st.m = m;
-  st.H = (double*)ws_get(c, "gd_H", sizeof(double) * 2 * (m + 1) * m * nrhs);
-  st.g = (double*)ws_get(c, "gd_g", sizeof(double) * 2 * (m + 1) * nrhs);
-  st.cs = (double*)ws_get(c, "gd_cs", sizeof(double) * m * nrhs);
-  st.sn = (double*)ws_get(c, "gd_sn", sizeof(double) * 2 * m * nrhs);
-  st.beta = (double*)ws_get(c, "gd_beta", sizeof(double) * nrhs);
+  st.H = (double*)ws_get(c, tag + "H", sizeof(double) * 2 * (m + 1) * m * nrhs);
+  st.g = (double*)ws_get(c, tag + "g", sizeof(double) * 2 * (m + 1) * nrhs);
+  st.cs = (double*)ws_get(c, tag + "cs", sizeof(double) * m * nrhs);
+  st.sn = (double*)ws_get(c, tag + "sn", sizeof(double) * 2 * m * nrhs);
+  st.beta = (double*)ws_get(c, tag + "beta", sizeof(double) * nrhs);
   if (!V || !w || !dots || !part || !coef || !a || !nrm || !st.H || !st.g || !st.cs || !st.sn || !st.beta)
     return set_err(c, QMG_E_NOMEM, "out of device memory (device GMRES)");
   const dim3 g1((nrhs + 63) / 64), b1(64);
@@ -141,7 +146,8 @@ qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const 
   }
   for (int j = 0; j < m && e == hipSuccess; ++j) {
     char* Vj = (char*)V + (size_t)j * bb;
-    e = launch_coarse_apply(c, p, w, Vj, tau, nrhs, s, qform);
+    e = fine ? launch_dslash(c, p, w, Vj, tau, nrhs, qform ? 1 : 0, s)
+             : launch_coarse_apply(c, p, w, Vj, tau, nrhs, s, qform);
     for (int pass = 0; pass < 1 && e == hipSuccess; ++pass) {
       e = launch_multidot(cp, dots, V, vs, j + 1, w, n, n, nrhs, part, s, 0);
       if (e == hipSuccess) {
@@ -161,4 +167,14 @@ qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const 
   if (e == hipSuccess) e = launch_multiaxpy(cp, y, V, vs, m, coef, n, n, nrhs, s);
   if (e != hipSuccess) return hip_err(c, e, "device GMRES");
   return QMG_OK;
+}
+
+qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
+                               hipStream_t s, int qform) {
+  return gmres_device(c, false, p, y, r, tau, nrhs, iters, s, qform);
+}
+
+qmg_status fine_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
+                             hipStream_t s, int qform) {
+  return gmres_device(c, true, p, y, r, tau, nrhs, iters, s, qform);
 }

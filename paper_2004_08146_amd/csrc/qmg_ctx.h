@@ -149,6 +149,11 @@ qmg_status solver_coarse_gmres(qmg_ctx* c, int p, void* y, const void* r, const 
                                int iters, double tol, int* iters_done, hipStream_t s, int qform = 0);
 qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
                                hipStream_t s, int qform = 0);
+// fixed-step device GMRES from zero on the fine stencil in precision p (smoother)
+qmg_status fine_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
+                             hipStream_t s, int qform = 0);
+// y += x for nrhs fields (n complex each, stride between fields)
+hipError_t launch_add(int p, void* y, const void* x, int64_t n, int64_t stride, int nrhs, hipStream_t s);
 // z = M r; z is written in precision zprec (FP64, or the preconditioner's own precision)
 qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs,
                          const qmg_params* prm, int* coarse_iters, hipStream_t s, int zprec = QMG_F64);

@@ -280,8 +280,8 @@ qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, 
   std::string key;
   {
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|", z, r, nrhs, prm->nu_post, prm->n_mr,
-                  prm->coarse_maxiter, (int)prm->mg_prec, prm->use_coarse, zprec, prm->q_form);
+    std::snprintf(buf, sizeof(buf), "%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%d|", z, r, nrhs, prm->nu_post, prm->n_mr,
+                  prm->coarse_maxiter, (int)prm->mg_prec, prm->use_coarse, zprec, prm->q_form, prm->smoother);
     key = buf;
     for (int k = 0; k < nrhs; ++k) {
       std::snprintf(buf, sizeof(buf), "%.17g,", tau[k]);
@@ -366,11 +366,26 @@ static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* 
     e = launch_fill_zero(zp, (size_t)n * nrhs * cbytes(p), s);
     if (e != hipSuccess) return hip_err(c, e, "zero");
   }
-  for (int sw = 0; sw < prm->nu_post; ++sw)
-    for (int col = 0; col < 2; ++col) {
-      e = launch_sap_colour(c, p, zp, rp, tau, nrhs, col, prm->n_mr, s, prm->q_form);
-      if (e != hipSuccess) return hip_err(c, e, "sap");
-    }
+  if (prm->smoother == 1 && prm->nu_post > 0) {
+    // GMRES smoothing (Sec. 2's alternative to SAP): nu_post fixed GMRES steps
+    // from zero on A e = r - A z, then z += e (A = D - tau Gamma5, or Q - tau)
+    void* az = ws_get(c, "vc_az", (size_t)n * nrhs * cbytes(p));
+    void* ez = ws_get(c, "vc_ez", (size_t)n * nrhs * cbytes(p));
+    if (!az || !ez) return set_err(c, QMG_E_NOMEM, "out of device memory (GMRES smoother)");
+    e = launch_dslash(c, p, az, zp, tau, nrhs, prm->q_form ? 1 : 0, s);
+    if (e == hipSuccess) e = launch_xmy(p, az, rp, n, n, nrhs, s);
+    if (e != hipSuccess) return hip_err(c, e, "smoother residual");
+    qmg_status st = fine_gmres_device(c, p, ez, az, tau, nrhs, prm->nu_post, s, prm->q_form);
+    if (st != QMG_OK) return st;
+    e = launch_add(p, zp, ez, n, n, nrhs, s);
+    if (e != hipSuccess) return hip_err(c, e, "smoother update");
+  } else {
+    for (int sw = 0; sw < prm->nu_post; ++sw)
+      for (int col = 0; col < 2; ++col) {
+        e = launch_sap_colour(c, p, zp, rp, tau, nrhs, col, prm->n_mr, s, prm->q_form);
+        if (e != hipSuccess) return hip_err(c, e, "sap");
+      }
+  }
   if (p != QMG_F64 && zprec != p) {
     e = launch_convert(z, QMG_F64, zp, p, n * nrhs, s);
     if (e != hipSuccess) return hip_err(c, e, "convert");

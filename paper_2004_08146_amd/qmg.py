@@ -35,7 +35,7 @@ class Params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("restart", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("n_mr", ctypes.c_int), ("coarse_maxiter", ctypes.c_int),
                 ("coarse_tol", ctypes.c_double), ("mg_prec", ctypes.c_int), ("use_coarse", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("q_form", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("q_form", ctypes.c_int), ("smoother", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
