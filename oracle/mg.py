@@ -154,6 +154,11 @@ class TwoLevel:
         rc = restrict(self.P, r, self.block)
         yc = gmres(lambda v: self.coarse.apply(v, tau, qform), rc, coarse_iters, coarse_tol)[0]
         z = prolong(self.P, yc, self.op.dims, self.block)
+        return self.post_smooth(r, z, tau, nu, n_mr, qform, smoother)
+
+    def post_smooth(self, r, z, tau, nu, n_mr, qform=False, smoother="sap"):
+        """nu post-smoothing steps on A_tau z = r from z (SAP sweeps, or GMRES
+        steps on the residual equation)."""
         if nu > 0 and smoother == "gmres":
             def A(v):
                 av = self.op.A(v, tau)
