@@ -86,6 +86,11 @@ typedef struct {
                           SAP and the coarse grid on Q - tau itself (the comparison of Sec. 3.3) */
   int smoother;        /* 0: red-black SAP (nu_post sweeps); 1: GMRES smoothing, nu_post fixed
                           GMRES steps on the fine residual equation (Sec. 2's alternative) */
+  int levels;          /* 2 (default), or 3: the coarse correction becomes coarse_maxiter steps of
+                          FGMRES on A_c (a K-cycle), right-preconditioned by the level-2 cycle
+                          (needs qmg_set_level3_vectors / qmg_setup_level3; always fixed steps) */
+  int l3_iters;        /* levels = 3: GMRES steps on the level-3 operator per level-2 cycle (20) */
+  int l2_smooth;       /* levels = 3: GMRES smoothing steps on level 2 per level-2 cycle (2) */
 } qmg_params;
 
 typedef struct {
@@ -193,6 +198,54 @@ qmg_status qmg_solve_shifted(qmg_ctx* ctx, void* x, const void* b, const double*
  * canonical complex128 device arrays; phi, x internal F64 fields. */
 qmg_status qmg_gauge_force(qmg_ctx* ctx, double* dU, double* dUbar, const void* phi,
                            const void* x, hipStream_t stream);
+
+/* ---- Third multigrid level.  The paper's solver (DD-alpha-AMG) is multilevel;
+ * its experiments use two levels (eq. (2.8), Sec. 4).  A third level repeats
+ * the first coarse level's construction (Sec. 2 aggregation, Sec. 3.1 P from
+ * test vectors) on the block lattice: aggregates of block2 level-2 sites (the
+ * lattice blocks), each split by coarse chirality, ntv2 test vectors per
+ * aggregate orthonormalised (modified Gram-Schmidt, two passes per column),
+ * Galerkin operator D3 = P2^H D_c P2 with self and 8 neighbour blocks.
+ *
+ * Level-2 vectors are the coarse vectors of qmg_restrict ([nrhs][nb][2 ntv],
+ * internal site order of qmg_coarse_site_order); level-3 vectors are
+ * [nrhs][n3][2 ntv2] with aggregates numbered lexicographically by aggregate
+ * coordinate (X_mu / block2_mu for block coordinate X), components
+ * [chirality +: j < ntv2, chirality -: j < ntv2].  Vectors are FP64 for
+ * QMG_F64 and FP32 otherwise, like the coarse vectors.
+ *
+ * qmg_set_level3_vectors: W2 holds ntv2 FP64 level-2 vectors (device), used
+ * as given.  block2 must divide the block lattice with >= 2 aggregates per
+ * direction; 1 <= ntv2 <= 24 and ntv2 <= bs2 * ntv (bs2 level-2 sites per
+ * aggregate, ntv components per chirality on level 2), bs2 * ntv <= 1024.  QMG_E_NUMERIC if the
+ * vectors are locally rank deficient; QMG_E_STATE before P / D_c exist.  A
+ * later rebuild of P / D_c (qmg_set_test_vectors, qmg_setup_mg, interpolation
+ * updates of the eigensolver) drops the level.  Synchronous. */
+qmg_status qmg_set_level3_vectors(qmg_ctx* ctx, const void* W2, int ntv2, const int block2[4],
+                                  hipStream_t stream);
+/* Setup of the level-2 test vectors (reading: the level-1 setup one level
+ * down): W2 (in/out, ntv2 FP64 level-2 vectors, e.g. P^H w_j of the level-1
+ * test vectors) is normalised, the level built, then setup_iters - 1 rounds of
+ * inverse iteration w <- M2(tau = 0) w (FP64; M2 with l3_iters level-3 GMRES
+ * steps and `smooth` level-2 GMRES smoothing steps), each normalised and
+ * followed by a rebuild.  Synchronous. */
+qmg_status qmg_setup_level3(qmg_ctx* ctx, void* W2, int ntv2, const int block2[4], int setup_iters, int smooth,
+                            int l3_iters, hipStream_t stream);
+/* y3 = P2^H y2 and y2 = P2 y3 (level-2 <-> level-3 vectors in the coarse precision of p). */
+qmg_status qmg_restrict_l3(qmg_ctx* ctx, void* y3, const void* y2, int nrhs, qmg_prec p, hipStream_t stream);
+qmg_status qmg_prolong_l3(qmg_ctx* ctx, void* y2, const void* y3, int nrhs, qmg_prec p, hipStream_t stream);
+/* out_k = (D3 - tau_k Gamma5^cc) in_k on level-3 vectors (D3 stored FP64, or FP32 for
+ * QMG_F32 / QMG_BF16). */
+qmg_status qmg_apply_l3(qmg_ctx* ctx, void* out, const void* in, const double* tau, int nrhs, qmg_prec p,
+                        hipStream_t stream);
+/* The level-2 solve of a three-level V-cycle: k2 FGMRES steps from zero on
+ * A_c(tau_k) y_k = r_k, right-preconditioned by the level-2 cycle M2 (k3 GMRES
+ * steps on A3 from zero on P2^H r, prolongation, s2 GMRES smoothing steps on the
+ * level-2 residual equation); every scalar stays on the device. */
+qmg_status qmg_level2_solve(qmg_ctx* ctx, void* y, const void* r, const double* tau, int nrhs, int k2, int k3,
+                            int s2, qmg_prec p, hipStream_t stream);
+/* Level-3 size: number of aggregates (level-3 sites) and components per site; 0, 0 before a build. */
+qmg_status qmg_level3_shape(const qmg_ctx* ctx, int* n3, int* nc3);
 
 /* Local coherence measure lc(v_k) = ||Pi v_k|| / ||v_k|| (Sec. 3.1), Pi the
  * orthogonal projection on the range of the current interpolation P; v:

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqmg.so")
 
-SOURCES = ["api", "layout", "gauge", "dslash", "sap", "transfer", "coarse", "blas", "force", "solver", "tune", "gmres_dev", "eigen"]
+SOURCES = ["api", "layout", "gauge", "dslash", "sap", "transfer", "coarse", "blas", "force", "solver", "tune", "gmres_dev", "eigen", "level3"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -90,6 +90,17 @@ qmg_status check_tau(qmg_ctx* c, const double* tau, int nrhs) {
   return QMG_OK;
 }
 
+// levels = 3 needs a built third level and sane step counts
+qmg_status check_levels(qmg_ctx* c, const qmg_params& p) {
+  if (p.levels != 2 && p.levels != 3) return set_err(c, QMG_E_ARG, "levels must be 2 or 3");
+  if (p.levels == 3 && p.use_coarse) {
+    if (p.l3_iters < 1 || p.l2_smooth < 0 || p.coarse_maxiter < 1)
+      return set_err(c, QMG_E_ARG, "levels = 3: need l3_iters >= 1, l2_smooth >= 0, coarse_maxiter >= 1");
+    if (!c->l3.ok) return set_err(c, QMG_E_STATE, "levels = 3: qmg_set_level3_vectors / qmg_setup_level3 has not been called");
+  }
+  return QMG_OK;
+}
+
 #define QMG_TRY(x)                  \
   do {                              \
     qmg_status _s = (x);            \
@@ -164,6 +175,9 @@ qmg_params qmg_default_params(void) {
   p.use_graph = 0;
   p.q_form = 0;
   p.smoother = 0;
+  p.levels = 2;
+  p.l3_iters = 20;
+  p.l2_smooth = 2;
   return p;
 }
 
@@ -490,6 +504,96 @@ qmg_status qmg_coarse_solve(qmg_ctx* c, void* y, const void* r, const double* ta
   return solver_coarse_gmres(c, p, y, r, tau, nrhs, iters, tol, nullptr, s);
 }
 
+// ---- third level
+static qmg_status check_block2(qmg_ctx* c, int ntv2, const int* block2) {
+  if (!block2 || ntv2 < 1 || ntv2 > 24) return set_err(c, QMG_E_ARG, "level 3: need 1 <= ntv2 <= 24");
+  int bs2 = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (block2[mu] < 1 || c->g.nbk[mu] % block2[mu] || c->g.nbk[mu] / block2[mu] < 2)
+      return set_err(c, QMG_E_ARG, "level 3: block2 must divide the block lattice with >= 2 aggregates per direction");
+    bs2 *= block2[mu];
+  }
+  if ((int64_t)bs2 * c->ntv > 1024) return set_err(c, QMG_E_ARG, "level 3: bs2 * ntv must be <= 1024");
+  if (ntv2 > bs2 * c->ntv) return set_err(c, QMG_E_ARG, "level 3: ntv2 exceeds the aggregate size");
+  return QMG_OK;
+}
+
+static qmg_status need_l3(qmg_ctx* c) {
+  QMG_TRY(need_mg(c));
+  if (!c->l3.ok) return set_err(c, QMG_E_STATE, "qmg_set_level3_vectors / qmg_setup_level3 has not been called");
+  return QMG_OK;
+}
+
+qmg_status qmg_set_level3_vectors(qmg_ctx* c, const void* W2, int ntv2, const int block2[4], hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(need_mg(c));
+  if (!W2) return set_err(c, QMG_E_ARG, "set_level3_vectors: null pointer");
+  QMG_TRY(check_block2(c, ntv2, block2));
+  hipSetDevice(c->device);
+  return build_l3(c, W2, ntv2, block2, s);
+}
+
+qmg_status qmg_setup_level3(qmg_ctx* c, void* W2, int ntv2, const int block2[4], int setup_iters, int smooth,
+                            int l3_iters, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(need_mg(c));
+  if (!W2 || setup_iters < 1 || smooth < 0 || l3_iters < 1) return set_err(c, QMG_E_ARG, "setup_level3: bad arguments");
+  QMG_TRY(check_block2(c, ntv2, block2));
+  hipSetDevice(c->device);
+  return solver_setup_l3(c, W2, ntv2, block2, setup_iters, smooth, l3_iters, s);
+}
+
+qmg_status qmg_restrict_l3(qmg_ctx* c, void* y3, const void* y2, int nrhs, qmg_prec p, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_l3(c));
+  if (!y3 || !y2) return set_err(c, QMG_E_ARG, "restrict_l3: null pointer");
+  hipSetDevice(c->device);
+  return hipchk(c, launch_restrict_l3(c, p, y3, y2, nrhs, s), "restrict_l3");
+}
+
+qmg_status qmg_prolong_l3(qmg_ctx* c, void* y2, const void* y3, int nrhs, qmg_prec p, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_l3(c));
+  if (!y3 || !y2) return set_err(c, QMG_E_ARG, "prolong_l3: null pointer");
+  hipSetDevice(c->device);
+  return hipchk(c, launch_prolong_l3(c, p, y2, y3, nrhs, s), "prolong_l3");
+}
+
+qmg_status qmg_apply_l3(qmg_ctx* c, void* out, const void* in, const double* tau, int nrhs, qmg_prec p,
+                        hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_l3(c));
+  QMG_TRY(check_tau(c, tau, nrhs));
+  if (!out || !in || out == in) return set_err(c, QMG_E_ARG, "apply_l3: bad pointers");
+  hipSetDevice(c->device);
+  return hipchk(c, launch_apply_l3(c, p, out, in, tau, nrhs, s), "apply_l3");
+}
+
+qmg_status qmg_level2_solve(qmg_ctx* c, void* y, const void* r, const double* tau, int nrhs, int k2, int k3, int s2,
+                            qmg_prec p, hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  QMG_TRY(need_l3(c));
+  QMG_TRY(check_tau(c, tau, nrhs));
+  if (!y || !r || y == r || k2 < 1 || k3 < 1 || s2 < 0) return set_err(c, QMG_E_ARG, "level2_solve: bad arguments");
+  hipSetDevice(c->device);
+  return level2_kcycle(c, p, y, r, tau, nrhs, k2, k3, s2, s);
+}
+
+qmg_status qmg_level3_shape(const qmg_ctx* c, int* n3, int* nc3) {
+  if (!c || !n3 || !nc3) return QMG_E_ARG;
+  *n3 = c->l3.ok ? c->l3.n3 : 0;
+  *nc3 = c->l3.ok ? 2 * c->l3.ntv2 : 0;
+  return QMG_OK;
+}
+
 qmg_status qmg_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
                       hipStream_t s) {
   if (!c) return QMG_E_ARG;
@@ -501,6 +605,7 @@ qmg_status qmg_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int
     return set_err(c, QMG_E_ARG, "vcycle: bad arguments");
   QMG_TRY(check_prec(c, prm->mg_prec));
   if (prm->use_coarse) QMG_TRY(need_mg(c));
+  QMG_TRY(check_levels(c, *prm));
   hipSetDevice(c->device);
   return solver_vcycle(c, z, r, tau, nrhs, prm, nullptr, s);
 }
@@ -518,6 +623,7 @@ qmg_status qmg_solve_shifted(qmg_ctx* c, void* x, const void* b, const double* t
   if (!(prm0.tol > 0) || prm0.maxiter < 1 || prm0.restart < 1 || prm0.nu_post < 0 || prm0.n_mr < 0 ||
       prm0.coarse_maxiter < 1 || prm0.q_form < 0 || prm0.q_form > 1 || prm0.smoother < 0 || prm0.smoother > 1)
     return set_err(c, QMG_E_ARG, "solve_shifted: bad parameters");
+  QMG_TRY(check_levels(c, prm0));
   if (prm0.use_coarse) QMG_TRY(need_mg(c));
   hipSetDevice(c->device);
   return solver_fgmres(c, x, b, tau, nrhs, &prm0, st, s);

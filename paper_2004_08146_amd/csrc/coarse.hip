@@ -8,6 +8,8 @@
 // restrict each part with the receiving block's P.  Blocks are stored
 // transposed, DcT[b][d][j][i] = D_c[b][d]_{ij}, d = 0 self, 1 + 2 mu for the
 // block at X + mu, 2 + 2 mu for X - mu (kept apart even when they coincide).
+// The apply kernels serve every coarse level: they take the level's neighbour
+// table, site count and blocks.
 #include "qmg_ctx.h"
 
 namespace {
@@ -58,16 +60,17 @@ struct TauArr {
 };
 
 template <typename S, typename C, int T>
-__global__ __launch_bounds__(64) void k_coarse_apply(Geom g, typename PT<C>::stor* out, const typename PT<S>::stor* DcT,
-                                                     const typename PT<C>::stor* in, int nc, int nrhs, TauArr tau) {
+__global__ __launch_bounds__(64) void k_coarse_apply(const int* nbr, int nb, typename PT<C>::stor* out,
+                                                     const typename PT<S>::stor* DcT, const typename PT<C>::stor* in,
+                                                     int nc, int nrhs, TauArr tau) {
   using R = typename PT<C>::real;
   __shared__ cpx<R> xin[9][T][64];
   const int b = blockIdx.x, k0 = blockIdx.y * T, tid = threadIdx.x;
   for (int idx = tid; idx < 9 * T * nc; idx += blockDim.x) {
     const int d = idx / (T * nc), t = (idx / nc) % T, j = idx % nc;
-    const int nbk = d == 0 ? b : g.nbr[b * 8 + d - 1];
+    const int nbk = d == 0 ? b : nbr[b * 8 + d - 1];
     const int k = k0 + t;
-    xin[d][t][j] = k < nrhs ? ldcv<R>(in, ((int64_t)k * g.nb + nbk) * nc + j) : czero<R>();
+    xin[d][t][j] = k < nrhs ? ldcv<R>(in, ((int64_t)k * nb + nbk) * nc + j) : czero<R>();
   }
   __syncthreads();
   const int i = tid;
@@ -88,7 +91,7 @@ __global__ __launch_bounds__(64) void k_coarse_apply(Geom g, typename PT<C>::sto
     const int k = k0 + t;
     if (k < nrhs) {
       const cpx<R> v = acc[t] - (R(tau.t[k]) * g5) * xin[0][t][i];
-      stcv(out, ((int64_t)k * g.nb + b) * nc + i, tau.qform ? g5 * v : v);
+      stcv(out, ((int64_t)k * nb + b) * nc + i, tau.qform ? g5 * v : v);
     }
   }
 }
@@ -114,8 +117,9 @@ template <> __device__ __forceinline__ int mrow<float>(int l, int r) { return 4 
 template <> __device__ __forceinline__ int mrow<double>(int l, int r) { return 4 * r + (l >> 4); }
 
 template <typename S, typename C, int NT>
-__global__ __launch_bounds__(64 * NT) void k_coarse_mfma(Geom g, typename PT<C>::stor* out, const typename PT<S>::stor* DcT,
-                                                    const typename PT<C>::stor* in, int nrhs, TauArr tau) {
+__global__ __launch_bounds__(64 * NT) void k_coarse_mfma(const int* nbr, int nb, typename PT<C>::stor* out,
+                                                         const typename PT<S>::stor* DcT, const typename PT<C>::stor* in,
+                                                         int nrhs, TauArr tau) {
   using R = typename PT<C>::real;
   using AT = typename MAcc<R>::T;
   constexpr int NC = 16 * NT;  // 2 ntv
@@ -129,11 +133,11 @@ __global__ __launch_bounds__(64 * NT) void k_coarse_mfma(Geom g, typename PT<C>:
   const auto* Db = DcT + (int64_t)b * 9 * NC * NC;
 #pragma unroll 1
   for (int d = 0; d < 9; ++d) {
-    const int nbk = d == 0 ? b : g.nbr[b * 8 + d - 1];
+    const int nbk = d == 0 ? b : nbr[b * 8 + d - 1];
     __syncthreads();
     for (int idx = tid; idx < NC * 16; idx += 64 * NT) {
       const int j = idx % NC, n = idx / NC;
-      const cpx<R> v = n0 + n < nrhs ? ldcv<R>(in, ((int64_t)(n0 + n) * g.nb + nbk) * NC + j) : czero<R>();
+      const cpx<R> v = n0 + n < nrhs ? ldcv<R>(in, ((int64_t)(n0 + n) * nb + nbk) * NC + j) : czero<R>();
       Bs[j][n] = v;
       if (d == 0) Bself[j][n] = v;
     }
@@ -159,24 +163,32 @@ __global__ __launch_bounds__(64 * NT) void k_coarse_mfma(Geom g, typename PT<C>:
     const cpx<R> self = Bself[i][ln];
     cpx<R> v = {acc_re[r] - tn * g5 * self.re, acc_im[r] - tn * g5 * self.im};
     if (tau.qform) v = g5 * v;
-    stcv(out, ((int64_t)n * g.nb + b) * NC + i, v);
+    stcv(out, ((int64_t)n * nb + b) * NC + i, v);
   }
 }
 
+// one coarse level's stencil: nb sites, 2 ntv components each, blocks D
+// (storage precision S) and the neighbour table
+struct CLevel {
+  const int* nbr;
+  int nb, ntv;
+  const void* D;
+};
+
 template <typename S>
-void capply_mfma(const qmg_ctx* c, int p, void* out, const void* in, const TauArr& tau, int nrhs, hipStream_t s) {
+void capply_mfma(const CLevel& lv, int p, void* out, const void* in, const TauArr& tau, int nrhs, hipStream_t s) {
   using P = typename PT<S>::stor;
-  dim3 grid(c->g.nb, (nrhs + 15) / 16);
+  dim3 grid(lv.nb, (nrhs + 15) / 16);
   // 2 ntv = 48 (ntv = 24) -> 3 row tiles; 2 ntv = 32 -> 2; 2 ntv = 16 -> 1
-  const int nt = (2 * c->ntv) / 16;
+  const int nt = (2 * lv.ntv) / 16;
   auto go = [&](auto ntc) {
     constexpr int NT = decltype(ntc)::value;
     if (p == QMG_F64)
-      hipLaunchKernelGGL((k_coarse_mfma<S, double, NT>), grid, dim3(64 * NT), 0, s, c->g, (double2*)out, (const P*)c->Dc[p],
-                         (const double2*)in, nrhs, tau);
+      hipLaunchKernelGGL((k_coarse_mfma<S, double, NT>), grid, dim3(64 * NT), 0, s, lv.nbr, lv.nb, (double2*)out,
+                         (const P*)lv.D, (const double2*)in, nrhs, tau);
     else
-      hipLaunchKernelGGL((k_coarse_mfma<S, float, NT>), grid, dim3(64 * NT), 0, s, c->g, (float2*)out, (const P*)c->Dc[p],
-                         (const float2*)in, nrhs, tau);
+      hipLaunchKernelGGL((k_coarse_mfma<S, float, NT>), grid, dim3(64 * NT), 0, s, lv.nbr, lv.nb, (float2*)out,
+                         (const P*)lv.D, (const float2*)in, nrhs, tau);
   };
   if (nt == 3) go(std::integral_constant<int, 3>{});
   else if (nt == 2) go(std::integral_constant<int, 2>{});
@@ -184,41 +196,37 @@ void capply_mfma(const qmg_ctx* c, int p, void* out, const void* in, const TauAr
 }
 
 template <typename S, int T>
-void capply_t(const qmg_ctx* c, int p, void* out, const void* in, const double* htau, int nrhs, hipStream_t s,
-              int qform) {
+void capply_t(const CLevel& lv, int p, void* out, const void* in, const TauArr& tau, int nrhs, hipStream_t s) {
   using P = typename PT<S>::stor;
-  TauArr dtau;
-  for (int i = 0; i < QMG_MAXRHS; ++i) dtau.t[i] = i < nrhs ? htau[i] : 0.0;
-  dtau.qform = qform;
-  const int nc = 2 * c->ntv;
-  dim3 grid(c->g.nb, (nrhs + T - 1) / T);
+  const int nc = 2 * lv.ntv;
+  dim3 grid(lv.nb, (nrhs + T - 1) / T);
   if (p == QMG_F64)
-    hipLaunchKernelGGL((k_coarse_apply<S, double, T>), grid, dim3(64), 0, s, c->g, (double2*)out,
-                       (const P*)c->Dc[p], (const double2*)in, nc, nrhs, dtau);
+    hipLaunchKernelGGL((k_coarse_apply<S, double, T>), grid, dim3(64), 0, s, lv.nbr, lv.nb, (double2*)out,
+                       (const P*)lv.D, (const double2*)in, nc, nrhs, tau);
   else
-    hipLaunchKernelGGL((k_coarse_apply<S, float, T>), grid, dim3(64), 0, s, c->g, (float2*)out,
-                       (const P*)c->Dc[p], (const float2*)in, nc, nrhs, dtau);
+    hipLaunchKernelGGL((k_coarse_apply<S, float, T>), grid, dim3(64), 0, s, lv.nbr, lv.nb, (float2*)out,
+                       (const P*)lv.D, (const float2*)in, nc, nrhs, tau);
 }
 
 template <typename S>
-void capply_s(const qmg_ctx* c, int p, void* out, const void* in, const double* dtau, int nrhs, hipStream_t s,
-              int qform) {
+void capply_s(const qmg_ctx* c, const CLevel& lv, int p, void* out, const void* in, const double* htau, int nrhs,
+              hipStream_t s, int qform) {
+  TauArr t;
+  for (int i = 0; i < QMG_MAXRHS; ++i) t.t[i] = i < nrhs ? htau[i] : 0.0;
+  t.qform = qform;
   // MFMA path when the coarse dimension is a multiple of 16 (ntv = 8, 16, 24) and
   // enough right-hand sides share each matrix block
-  if (c->tune.coarse_mfma && (2 * c->ntv) % 16 == 0 && 2 * c->ntv <= 48 && nrhs >= c->tune.coarse_mfma_min_rhs) {
-    TauArr t;
-    for (int i = 0; i < QMG_MAXRHS; ++i) t.t[i] = i < nrhs ? dtau[i] : 0.0;
-    t.qform = qform;
+  if (c->tune.coarse_mfma && (2 * lv.ntv) % 16 == 0 && 2 * lv.ntv <= 48 && nrhs >= c->tune.coarse_mfma_min_rhs) {
     if constexpr (std::is_same<S, double>::value) {
-      if (p == QMG_F64) { capply_mfma<S>(c, p, out, in, t, nrhs, s); return; }
+      if (p == QMG_F64) { capply_mfma<S>(lv, p, out, in, t, nrhs, s); return; }
     } else {
-      capply_mfma<S>(c, p, out, in, t, nrhs, s);
+      capply_mfma<S>(lv, p, out, in, t, nrhs, s);
       return;
     }
   }
-  if (nrhs >= 4) capply_t<S, 4>(c, p, out, in, dtau, nrhs, s, qform);
-  else if (nrhs == 2) capply_t<S, 2>(c, p, out, in, dtau, nrhs, s, qform);
-  else capply_t<S, 1>(c, p, out, in, dtau, nrhs, s, qform);
+  if (nrhs >= 4) capply_t<S, 4>(lv, p, out, in, t, nrhs, s);
+  else if (nrhs == 2) capply_t<S, 2>(lv, p, out, in, t, nrhs, s);
+  else capply_t<S, 1>(lv, p, out, in, t, nrhs, s);
 }
 
 }  // namespace
@@ -233,8 +241,19 @@ hipError_t launch_split_stencil(const qmg_ctx* c, void* out9, const void* in, hi
 // tau: host array of nrhs shifts
 hipError_t launch_coarse_apply(const qmg_ctx* c, int p, void* out, const void* in, const double* dtau, int nrhs,
                                hipStream_t s, int qform) {
-  if (p == QMG_F64) capply_s<double>(c, p, out, in, dtau, nrhs, s, qform);
-  else if (p == QMG_F32) capply_s<float>(c, p, out, in, dtau, nrhs, s, qform);
-  else capply_s<bf16_t>(c, p, out, in, dtau, nrhs, s, qform);
+  const CLevel lv{c->g.nbr, c->g.nb, c->ntv, c->Dc[p]};
+  if (p == QMG_F64) capply_s<double>(c, lv, p, out, in, dtau, nrhs, s, qform);
+  else if (p == QMG_F32) capply_s<float>(c, lv, p, out, in, dtau, nrhs, s, qform);
+  else capply_s<bf16_t>(c, lv, p, out, in, dtau, nrhs, s, qform);
+  return hipGetLastError();
+}
+
+// level-3 operator A3(tau) = D3 - tau Gamma5^cc (D3 stored in the coarse precision of p)
+hipError_t launch_apply_l3(const qmg_ctx* c, int p, void* out, const void* in, const double* dtau, int nrhs,
+                           hipStream_t s, int qform) {
+  const int sp = p == QMG_F64 ? 0 : 1;
+  const CLevel lv{c->l3.nbr3, c->l3.n3, c->l3.ntv2, c->l3.D3[sp]};
+  if (p == QMG_F64) capply_s<double>(c, lv, p, out, in, dtau, nrhs, s, qform);
+  else capply_s<float>(c, lv, p, out, in, dtau, nrhs, s, qform);
   return hipGetLastError();
 }

@@ -1,10 +1,13 @@
 // Device-resident GMRES scalars (Hessenberg column, Givens rotations,
 // back-substitution) so a fixed-step coarse GMRES -- and with it the whole
 // V-cycle -- runs without host round trips and can be captured in a HIP graph.
+// The same driver runs the GMRES smoother on the fine level and, with a third
+// level, the level-3 GMRES and the level-2 flexible GMRES (K-cycle).
 // Being part of the preconditioner, this coarse GMRES makes a single classical
 // Gram-Schmidt pass per step (no data-dependent second pass).
 // One thread per right-hand side; the rotations follow the same convention as
 // the host solver: [[c, s], [-conj(s), c]] [a; b] = [r; 0], c real.
+#include <functional>
 #include <string>
 
 #include "qmg_ctx.h"
@@ -109,33 +112,46 @@ __global__ void k_gm_solve(GmState st, double* coef, int kk, int nrhs) {
 
 }  // namespace
 
-// Fixed-step GMRES from zero with every scalar on the device (graph-capturable),
-// on the coarse operator (fine = false, coarse precision of p) or on the fine
-// stencil in precision p (fine = true; the smoother of Sec. 2's GMRES option).
-// Work buffers come from ws (allocate them before a capture with the same sizes).
-static qmg_status gmres_device(qmg_ctx* c, bool fine, int p, void* y, const void* r, const double* tau, int nrhs,
-                               int iters, hipStream_t s, int qform) {
-  const int cp = fine ? p : coarse_prec(p);
-  const int64_t n = fine ? (int64_t)field_elems(c) : (int64_t)coarse_elems(c);
+// The operator of a device GMRES run: n complex elements per right-hand side
+// in storage precision cp; prec set: flexible GMRES, right-preconditioned by
+// prec (the preconditioned directions are kept and form the update).
+struct DevOp {
+  int64_t n;
+  int cp;
+  std::string tag;  // workspace name prefix (nested runs need distinct tags)
+  std::function<hipError_t(void* out, const void* in)> apply;
+  std::function<qmg_status(void* z, const void* v)> prec;
+};
+
+// Fixed-step (F)GMRES from zero with every scalar on the device
+// (graph-capturable).  Work buffers come from ws (allocate them before a
+// capture with the same sizes).
+static qmg_status gmres_device(qmg_ctx* c, const DevOp& op, void* y, const void* r, int nrhs, int iters,
+                               hipStream_t s) {
+  const int cp = op.cp;
+  const int64_t n = op.n;
   const size_t vb = (size_t)n * cbytes(cp);
   const size_t bb = vb * nrhs;
   const int m = iters;
-  const std::string tag = fine ? "fd_" : "gd_";
-  void* V = ws_get(c, fine ? "fs_V" : "cg_V", bb * (m + 1));
-  void* w = ws_get(c, fine ? "fs_w" : "cg_w", bb);
-  double* dots = (double*)ws_get(c, tag + "dots", sizeof(double) * 2 * (m + 2) * nrhs);
-  double* part = (double*)ws_get(c, tag + "part", sizeof(double) * multidot_partial_doubles(n, m + 2, nrhs));
-  double* coef = (double*)ws_get(c, tag + "coef", sizeof(double) * 2 * (m + 1) * nrhs);
-  double* a = (double*)ws_get(c, tag + "a", sizeof(double) * 2 * nrhs);
-  double* nrm = (double*)ws_get(c, tag + "nrm", sizeof(double) * 2 * nrhs);
+  const std::string& tag = op.tag;
+  const bool flex = (bool)op.prec;
+  void* V = ws_get(c, tag + "_V", bb * (m + 1));
+  void* w = ws_get(c, tag + "_w", bb);
+  void* Z = flex ? ws_get(c, tag + "_Z", bb * m) : nullptr;
+  double* dots = (double*)ws_get(c, tag + "_dots", sizeof(double) * 2 * (m + 2) * nrhs);
+  double* part = (double*)ws_get(c, tag + "_part", sizeof(double) * multidot_partial_doubles(n, m + 2, nrhs));
+  double* coef = (double*)ws_get(c, tag + "_coef", sizeof(double) * 2 * (m + 1) * nrhs);
+  double* a = (double*)ws_get(c, tag + "_a", sizeof(double) * 2 * nrhs);
+  double* nrm = (double*)ws_get(c, tag + "_nrm", sizeof(double) * 2 * nrhs);
   GmState st;
   st.m = m;
-  st.H = (double*)ws_get(c, tag + "H", sizeof(double) * 2 * (m + 1) * m * nrhs);
-  st.g = (double*)ws_get(c, tag + "g", sizeof(double) * 2 * (m + 1) * nrhs);
-  st.cs = (double*)ws_get(c, tag + "cs", sizeof(double) * m * nrhs);
-  st.sn = (double*)ws_get(c, tag + "sn", sizeof(double) * 2 * m * nrhs);
-  st.beta = (double*)ws_get(c, tag + "beta", sizeof(double) * nrhs);
-  if (!V || !w || !dots || !part || !coef || !a || !nrm || !st.H || !st.g || !st.cs || !st.sn || !st.beta)
+  st.H = (double*)ws_get(c, tag + "_H", sizeof(double) * 2 * (m + 1) * m * nrhs);
+  st.g = (double*)ws_get(c, tag + "_g", sizeof(double) * 2 * (m + 1) * nrhs);
+  st.cs = (double*)ws_get(c, tag + "_cs", sizeof(double) * m * nrhs);
+  st.sn = (double*)ws_get(c, tag + "_sn", sizeof(double) * 2 * m * nrhs);
+  st.beta = (double*)ws_get(c, tag + "_beta", sizeof(double) * nrhs);
+  if (!V || !w || (flex && !Z) || !dots || !part || !coef || !a || !nrm || !st.H || !st.g || !st.cs || !st.sn ||
+      !st.beta)
     return set_err(c, QMG_E_NOMEM, "out of device memory (device GMRES)");
   const dim3 g1((nrhs + 63) / 64), b1(64);
   const int64_t vs = n * nrhs;
@@ -146,14 +162,18 @@ static qmg_status gmres_device(qmg_ctx* c, bool fine, int p, void* y, const void
   }
   for (int j = 0; j < m && e == hipSuccess; ++j) {
     char* Vj = (char*)V + (size_t)j * bb;
-    e = fine ? launch_dslash(c, p, w, Vj, tau, nrhs, qform ? 1 : 0, s)
-             : launch_coarse_apply(c, p, w, Vj, tau, nrhs, s, qform);
-    for (int pass = 0; pass < 1 && e == hipSuccess; ++pass) {
-      e = launch_multidot(cp, dots, V, vs, j + 1, w, n, n, nrhs, part, s, 0);
-      if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_gm_coef, g1, b1, 0, s, st, dots, coef, j, nrhs);
-        e = launch_axpy_norm(cp, w, V, vs, j + 1, coef, n, n, nrhs, nrm, part, s);
-      }
+    if (flex) {
+      char* Zj = (char*)Z + (size_t)j * bb;
+      qmg_status ps = op.prec(Zj, Vj);
+      if (ps != QMG_OK) return ps;
+      e = op.apply(w, Zj);
+    } else {
+      e = op.apply(w, Vj);
+    }
+    if (e == hipSuccess) e = launch_multidot(cp, dots, V, vs, j + 1, w, n, n, nrhs, part, s, 0);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_gm_coef, g1, b1, 0, s, st, dots, coef, j, nrhs);
+      e = launch_axpy_norm(cp, w, V, vs, j + 1, coef, n, n, nrhs, nrm, part, s);
     }
     if (e == hipSuccess) {
       hipLaunchKernelGGL(k_gm_col, g1, b1, 0, s, st, nrm, a, j, nrhs);
@@ -164,17 +184,67 @@ static qmg_status gmres_device(qmg_ctx* c, bool fine, int p, void* y, const void
     hipLaunchKernelGGL(k_gm_solve, g1, b1, 0, s, st, coef, m, nrhs);
     e = launch_fill_zero(y, bb, s);
   }
-  if (e == hipSuccess) e = launch_multiaxpy(cp, y, V, vs, m, coef, n, n, nrhs, s);
+  if (e == hipSuccess) e = launch_multiaxpy(cp, y, flex ? Z : V, vs, m, coef, n, n, nrhs, s);
   if (e != hipSuccess) return hip_err(c, e, "device GMRES");
   return QMG_OK;
 }
 
+// GMRES on the coarse operator (coarse precision of p); shares its basis
+// buffers with the host-driven coarse GMRES (never live at the same time)
 qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
                                hipStream_t s, int qform) {
-  return gmres_device(c, false, p, y, r, tau, nrhs, iters, s, qform);
+  DevOp op{(int64_t)coarse_elems(c), coarse_prec(p), "cg",
+           [=](void* out, const void* in) { return launch_coarse_apply(c, p, out, in, tau, nrhs, s, qform); }, {}};
+  return gmres_device(c, op, y, r, nrhs, iters, s);
 }
 
+// GMRES on the fine stencil in precision p (the smoother of Sec. 2's GMRES option)
 qmg_status fine_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
                              hipStream_t s, int qform) {
-  return gmres_device(c, true, p, y, r, tau, nrhs, iters, s, qform);
+  DevOp op{(int64_t)field_elems(c), p, "fs",
+           [=](void* out, const void* in) { return launch_dslash(c, p, out, in, tau, nrhs, qform ? 1 : 0, s); }, {}};
+  return gmres_device(c, op, y, r, nrhs, iters, s);
+}
+
+// ---- third level.  M2 r2 = z: P2 y3 with y3 from k3 GMRES steps on
+// A3(tau) y3 = P2^H r2, then s2 GMRES steps from zero on A_c e = r2 - A_c z
+// and z + e.  Level-2 and level-3 vectors are in the coarse precision of p.
+qmg_status level2_cycle(qmg_ctx* c, int p, void* z, const void* r, const double* tau, int nrhs, int k3, int s2,
+                        hipStream_t s, int qform) {
+  const int cp = coarse_prec(p);
+  const int64_t n2 = (int64_t)coarse_elems(c), n3 = (int64_t)l3_elems(c);
+  void* r3 = ws_get(c, "l3_r", (size_t)n3 * nrhs * cbytes(cp));
+  void* y3 = ws_get(c, "l3_y", (size_t)n3 * nrhs * cbytes(cp));
+  if (!r3 || !y3) return set_err(c, QMG_E_NOMEM, "out of device memory (level-2 cycle)");
+  hipError_t e = launch_restrict_l3(c, p, r3, r, nrhs, s);
+  if (e != hipSuccess) return hip_err(c, e, "restrict to level 3");
+  DevOp op3{n3, cp, "l3g",
+            [=](void* out, const void* in) { return launch_apply_l3(c, p, out, in, tau, nrhs, s, qform); }, {}};
+  qmg_status st = gmres_device(c, op3, y3, r3, nrhs, k3, s);
+  if (st != QMG_OK) return st;
+  e = launch_prolong_l3(c, p, z, y3, nrhs, s);
+  if (e != hipSuccess) return hip_err(c, e, "prolong from level 3");
+  if (s2 > 0) {
+    void* az = ws_get(c, "l2_az", (size_t)n2 * nrhs * cbytes(cp));
+    void* ez = ws_get(c, "l2_ez", (size_t)n2 * nrhs * cbytes(cp));
+    if (!az || !ez) return set_err(c, QMG_E_NOMEM, "out of device memory (level-2 smoothing)");
+    e = launch_coarse_apply(c, p, az, z, tau, nrhs, s, qform);
+    if (e == hipSuccess) e = launch_xmy(cp, az, r, n2, n2, nrhs, s);
+    if (e != hipSuccess) return hip_err(c, e, "level-2 smoothing residual");
+    st = coarse_gmres_device(c, p, ez, az, tau, nrhs, s2, s, qform);
+    if (st != QMG_OK) return st;
+    e = launch_add(cp, z, ez, n2, n2, nrhs, s);
+    if (e != hipSuccess) return hip_err(c, e, "level-2 smoothing update");
+  }
+  return QMG_OK;
+}
+
+// k2 FGMRES steps from zero on A_c(tau) y = r, right-preconditioned by M2
+// (a K-cycle on level 2)
+qmg_status level2_kcycle(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int k2, int k3,
+                         int s2, hipStream_t s, int qform) {
+  DevOp op{(int64_t)coarse_elems(c), coarse_prec(p), "kc",
+           [=](void* out, const void* in) { return launch_coarse_apply(c, p, out, in, tau, nrhs, s, qform); },
+           [=](void* z, const void* v) { return level2_cycle(c, p, z, v, tau, nrhs, k3, s2, s, qform); }};
+  return gmres_device(c, op, y, r, nrhs, k2, s);
 }

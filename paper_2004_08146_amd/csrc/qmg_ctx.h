@@ -44,6 +44,23 @@ struct Tune {
   bool tuned = false;
 };
 
+// Third multigrid level: aggregates of block2 level-2 sites (lattice blocks),
+// ntv2 level-3 components per chirality.  Tables and operators live in the
+// workspace; the level is dropped whenever P / D_c are rebuilt.
+struct Level3 {
+  bool ok = false;
+  int ntv2 = 0, n3 = 0, bs2 = 0;
+  int block2[4] = {0, 0, 0, 0};
+  int dims3[4] = {0, 0, 0, 0};
+  const int* sites = nullptr;  // [n3][bs2] level-2 site ids, lexicographic inside the aggregate
+  const int* agg = nullptr;    // [nb] aggregate of each level-2 site
+  const int* qloc = nullptr;   // [nb] index of the site inside its aggregate
+  const int* keep = nullptr;   // [nb][9] 1 where stencil entry d of the site stays in its aggregate
+  const int* nbr3 = nullptr;   // [n3][8] level-3 neighbours: 2 mu forward, 2 mu + 1 backward
+  void* P2[2] = {nullptr, nullptr};  // F64, F32: [n3][2][bs2 * ntv][ntv2]
+  void* D3[2] = {nullptr, nullptr};  // F64, F32: [n3][9][2 ntv2][2 ntv2] (transposed blocks)
+};
+
 struct qmg_ctx {
   int device = 0;
   Geom g{};                    // device pointers for tables inside
@@ -66,6 +83,7 @@ struct qmg_ctx {
   int ntv = 0;
   void* P[3] = {nullptr, nullptr, nullptr};
   void* Dc[3] = {nullptr, nullptr, nullptr};
+  Level3 l3;
   // workspace
   std::map<std::string, std::pair<void*, size_t>> ws;
   std::map<std::string, std::vector<double>> hbuf;  // host staging for small Krylov data
@@ -78,6 +96,7 @@ struct qmg_ctx {
 
 size_t field_elems(const qmg_ctx* c);   // complex elements in one fine field
 size_t coarse_elems(const qmg_ctx* c);  // complex elements in one coarse vector
+size_t l3_elems(const qmg_ctx* c);      // complex elements in one level-3 vector
 
 // stencil work order (tile shape index into kTileShapes); synchronous, not for use under capture
 qmg_status set_ds_order(qmg_ctx* c, int order);
@@ -116,6 +135,15 @@ hipError_t launch_restrict_into_dc(const qmg_ctx* c, void* Dc64, const void* in9
                                    hipStream_t s);
 hipError_t launch_coarse_apply(const qmg_ctx* c, int p, void* out, const void* in, const double* tau,
                                int nrhs, hipStream_t s, int qform = 0);  // tau: host array
+// level-3 operator A3(tau) = D3 - tau Gamma5^cc on level-3 vectors of the coarse precision of p
+hipError_t launch_apply_l3(const qmg_ctx* c, int p, void* out, const void* in, const double* tau, int nrhs,
+                           hipStream_t s, int qform = 0);
+// ---- level3.hip (level-2 and level-3 vectors in the coarse precision of p)
+qmg_status build_l3(qmg_ctx* c, const void* W2, int ntv2, const int block2[4], hipStream_t s);
+hipError_t launch_restrict_l3(const qmg_ctx* c, int p, void* y3, const void* y2, int nrhs, hipStream_t s);
+hipError_t launch_prolong_l3(const qmg_ctx* c, int p, void* y2, const void* y3, int nrhs, hipStream_t s);
+qmg_status solver_setup_l3(qmg_ctx* c, void* W2, int ntv2, const int block2[4], int iters, int s2, int k3,
+                           hipStream_t s);
 // ---- blas.hip (vectors of n complex per right-hand side, k-th rhs at offset k*stride)
 // dots[k*J + j] = <V_j,k , w_k> for j < J (V_j at base + j*vstride), FP64 results on device
 hipError_t launch_multidot(int p, double* dots, const void* V, int64_t vstride, int J, const void* w,
@@ -152,6 +180,12 @@ qmg_status coarse_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const 
 // fixed-step device GMRES from zero on the fine stencil in precision p (smoother)
 qmg_status fine_gmres_device(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int iters,
                              hipStream_t s, int qform = 0);
+// the level-2 cycle M2 (level-3 GMRES correction, level-2 GMRES smoothing) and
+// k2 steps of level-2 FGMRES preconditioned by it
+qmg_status level2_cycle(qmg_ctx* c, int p, void* z, const void* r, const double* tau, int nrhs, int k3, int s2,
+                        hipStream_t s, int qform = 0);
+qmg_status level2_kcycle(qmg_ctx* c, int p, void* y, const void* r, const double* tau, int nrhs, int k2, int k3,
+                         int s2, hipStream_t s, int qform = 0);
 // y += x for nrhs fields (n complex each, stride between fields)
 hipError_t launch_add(int p, void* y, const void* x, int64_t n, int64_t stride, int nrhs, hipStream_t s);
 // z = M r; z is written in precision zprec (FP64, or the preconditioner's own precision)

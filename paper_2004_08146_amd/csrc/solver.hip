@@ -280,8 +280,9 @@ qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, 
   std::string key;
   {
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%d|", z, r, nrhs, prm->nu_post, prm->n_mr,
-                  prm->coarse_maxiter, (int)prm->mg_prec, prm->use_coarse, zprec, prm->q_form, prm->smoother);
+    std::snprintf(buf, sizeof(buf), "%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|", z, r, nrhs, prm->nu_post,
+                  prm->n_mr, prm->coarse_maxiter, (int)prm->mg_prec, prm->use_coarse, zprec, prm->q_form,
+                  prm->smoother, prm->levels, prm->l3_iters, prm->l2_smooth);
     key = buf;
     for (int k = 0; k < nrhs; ++k) {
       std::snprintf(buf, sizeof(buf), "%.17g,", tau[k]);
@@ -352,11 +353,16 @@ static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* 
     if (e != hipSuccess) return hip_err(c, e, "restrict");
     int it = 0;
     // a fixed number of coarse steps (graph mode, or coarse_tol <= 0) runs the
-    // device-resident GMRES, which never waits for the host
-    const bool fixed = graph_safe || !(prm->coarse_tol > 0);
-    qmg_status st = fixed ? coarse_gmres_device(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, s, prm->q_form)
-                          : solver_coarse_gmres(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, prm->coarse_tol,
-                                                &it, s, prm->q_form);
+    // device-resident GMRES, which never waits for the host; three levels
+    // always take coarse_maxiter K-cycle steps on level 2
+    const bool three = prm->levels == 3;
+    const bool fixed = three || graph_safe || !(prm->coarse_tol > 0);
+    qmg_status st =
+        three ? level2_kcycle(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, prm->l3_iters, prm->l2_smooth, s,
+                              prm->q_form)
+        : fixed ? coarse_gmres_device(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, s, prm->q_form)
+                : solver_coarse_gmres(c, p, yc, rc, tau, nrhs, prm->coarse_maxiter, prm->coarse_tol, &it, s,
+                                      prm->q_form);
     if (st != QMG_OK) return st;
     if (fixed) it = prm->coarse_maxiter;
     if (coarse_iters) *coarse_iters += it;
@@ -528,6 +534,7 @@ qmg_status build_mg(qmg_ctx* c, const void* W, int ntv, hipStream_t s) {
   const size_t pel = (size_t)g.nb * 2 * ntv * 6 * ((size_t)1 << g.bs_log);
   const size_t del = (size_t)g.nb * 9 * nc * nc;
   c->have_mg = false;
+  c->l3.ok = false;  // the third level is built on D_c
   c->ntv = ntv;
   drop_graphs(c);
   for (int p = 0; p < 3; ++p) {

@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("restart", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("n_mr", ctypes.c_int), ("coarse_maxiter", ctypes.c_int),
                 ("coarse_tol", ctypes.c_double), ("mg_prec", ctypes.c_int), ("use_coarse", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("q_form", ctypes.c_int), ("smoother", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("q_form", ctypes.c_int), ("smoother", ctypes.c_int),
+                ("levels", ctypes.c_int), ("l3_iters", ctypes.c_int), ("l2_smooth", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -95,6 +96,13 @@ _SIG = {
     "qmg_eigensolve": ([_vp, _i, _dp, _vp, _vp, _i, _vp, ctypes.POINTER(EigParams), ctypes.POINTER(EigStats),
                         _vp], _i),
     "qmg_hermitian_eig": ([_i, _dp, _dp, _dp], _i),
+    "qmg_set_level3_vectors": ([_vp, _vp, _i, ctypes.POINTER(_i), _vp], _i),
+    "qmg_setup_level3": ([_vp, _vp, _i, ctypes.POINTER(_i), _i, _i, _i, _vp], _i),
+    "qmg_restrict_l3": ([_vp, _vp, _vp, _i, _i, _vp], _i),
+    "qmg_prolong_l3": ([_vp, _vp, _vp, _i, _i, _vp], _i),
+    "qmg_apply_l3": ([_vp, _vp, _vp, _dp, _i, _i, _vp], _i),
+    "qmg_level2_solve": ([_vp, _vp, _vp, _dp, _i, _i, _i, _i, _i, _vp], _i),
+    "qmg_level3_shape": ([_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
 }
 for _name, (_args, _res) in _SIG.items():
     _f = getattr(_lib, _name)
@@ -282,6 +290,57 @@ class Lattice:
     def coarse_solve(self, y, r, tau, nrhs=1, iters=20, tol=0.0, prec="f64"):
         self._check(_lib.qmg_coarse_solve(self._h, _ptr(y), _ptr(r), _taus(tau, nrhs), nrhs, iters,
                                           float(tol), _PREC[prec], _stream()), "coarse_solve")
+        return y
+
+    # ------------------------------------------------------- third level --
+    def set_level3_vectors(self, W2, ntv2, block2):
+        """W2: ntv2 FP64 level-2 (coarse) vectors on the device, internal site order."""
+        b2 = (ctypes.c_int * 4)(*block2)
+        self._check(_lib.qmg_set_level3_vectors(self._h, _ptr(W2), ntv2, b2, _stream()), "set_level3_vectors")
+
+    def setup_level3(self, W2, ntv2, block2, setup_iters=3, smooth=2, l3_iters=20):
+        """Level-2 test vectors by inverse iteration (W2 updated in place)."""
+        b2 = (ctypes.c_int * 4)(*block2)
+        self._check(_lib.qmg_setup_level3(self._h, _ptr(W2), ntv2, b2, setup_iters, smooth, l3_iters, _stream()),
+                    "setup_level3")
+        return W2
+
+    def level2_vectors_from(self, W, ntv2):
+        """P^H w_j of the first ntv2 fine FP64 test vectors W (internal layout):
+        starting level-2 vectors for setup_level3."""
+        fb = self.field_bytes("f64")
+        out = self.coarse(ntv2)
+        cb = self.coarse_bytes("f64")
+        for j in range(ntv2):
+            self.restrict(out[j * cb:(j + 1) * cb], W[j * fb:(j + 1) * fb], 1)
+        return out
+
+    def level3_shape(self):
+        n3, nc3 = ctypes.c_int(), ctypes.c_int()
+        self._check(_lib.qmg_level3_shape(self._h, ctypes.byref(n3), ctypes.byref(nc3)), "level3_shape")
+        return n3.value, nc3.value
+
+    def l3_vec(self, nrhs=1, prec="f64"):
+        n3, nc3 = self.level3_shape()
+        itemsize = 16 if prec == "f64" else 8
+        return torch.zeros(n3 * nc3 * nrhs * itemsize, dtype=torch.uint8, device=self.device)
+
+    def restrict_l3(self, y3, y2, nrhs=1, prec="f64"):
+        self._check(_lib.qmg_restrict_l3(self._h, _ptr(y3), _ptr(y2), nrhs, _PREC[prec], _stream()), "restrict_l3")
+        return y3
+
+    def prolong_l3(self, y2, y3, nrhs=1, prec="f64"):
+        self._check(_lib.qmg_prolong_l3(self._h, _ptr(y2), _ptr(y3), nrhs, _PREC[prec], _stream()), "prolong_l3")
+        return y2
+
+    def apply_l3(self, out, inp, tau, nrhs=1, prec="f64"):
+        self._check(_lib.qmg_apply_l3(self._h, _ptr(out), _ptr(inp), _taus(tau, nrhs), nrhs, _PREC[prec],
+                                      _stream()), "apply_l3")
+        return out
+
+    def level2_solve(self, y, r, tau, nrhs=1, k2=4, k3=20, s2=2, prec="f64"):
+        self._check(_lib.qmg_level2_solve(self._h, _ptr(y), _ptr(r), _taus(tau, nrhs), nrhs, k2, k3, s2,
+                                          _PREC[prec], _stream()), "level2_solve")
         return y
 
     def vcycle(self, z, r, tau, nrhs=1, params=None):
