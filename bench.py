@@ -309,7 +309,10 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the extra FP64/BF16 solves")
     ap.add_argument("--tune-cache", type=str, default=None, help="autotuner JSON cache (default: fresh)")
     ap.add_argument("--graph", type=int, default=1, help="1: V-cycle replayed as a HIP graph (fixed coarse steps)")
-    ap.add_argument("--coarse-iters", type=int, default=16, help="coarse GMRES steps in graph mode")
+    ap.add_argument("--coarse-iters", type=int, default=20, help="coarse GMRES steps in graph mode")
+    ap.add_argument("--l3", type=str, default="4,8,2",
+                    help="three-level leg: K-cycle steps k2, level-3 GMRES steps k3, level-2 smoothing steps s2 "
+                         "('' to skip)")
     ap.add_argument("--variant", type=int, default=None, help="kernels mode: pin this stencil variant")
     ap.add_argument("--remap", type=int, default=1, help="kernels mode: XCD-aware work-group mapping (with --variant)")
     ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",
@@ -362,6 +365,8 @@ def main():
     lat.setup_mg(W0, ntv, setup_iters=args.setup_iters, smooth=4, n_mr=3, coarse_maxiter=20, coarse_tol=0.5)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
+    # starting level-2 vectors of the three-level leg: P^H w_j of the level-1 test vectors
+    W2 = lat.level2_vectors_from(W0, ntv) if args.l3 and not args.quick else None
     del W0
     print("[bench] setup %.2f s" % setup_s, file=sys.stderr, flush=True)
     tune_path = args.tune_cache or os.path.join("/tmp", "qmg_tune_%d.json" % os.getpid())
@@ -415,6 +420,31 @@ def main():
                            "max_true_relres": max(s["true_relres"] for s in stats),
                            "iters": [s["iters"] for s in stats]}
             print("[bench] %s solve %.1f ms" % (prec, extra[prec]["ms"]), file=sys.stderr, flush=True)
+
+    if W2 is not None:
+        # third level: aggregates of 2^4 blocks, 24 level-2 test vectors improved by two rounds of
+        # inverse iteration; the coarse correction is a K-cycle on level 2
+        k2, k3, s2 = (int(v) for v in args.l3.split(","))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lat.setup_level3(W2, ntv, (2, 2, 2, 2), setup_iters=3, smooth=s2, l3_iters=20)
+        torch.cuda.synchronize()
+        l3_setup = time.perf_counter() - t1
+        del W2
+        prm3 = qmg.default_params(mg_prec="f32", restart=args.restart, maxiter=args.maxiter, use_graph=1,
+                                  levels=3, coarse_maxiter=k2, l3_iters=k3, l2_smooth=s2)
+        x3 = lat.field(nrhs)
+        lat.solve_shifted(x3, bg, taus, nrhs, prm3)  # records the three-level V-cycle graph
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, stats = lat.solve_shifted(x3, bg, taus, nrhs, prm3)
+        torch.cuda.synchronize()
+        extra["f32_three_level"] = {"ms": 1000.0 * (time.perf_counter() - t1), "status": st,
+                                    "max_true_relres": max(s["true_relres"] for s in stats),
+                                    "iters": [s["iters"] for s in stats], "level3_setup_s": l3_setup,
+                                    "k2": k2, "k3": k3, "s2": s2, "ntv2": ntv, "block2": [2, 2, 2, 2]}
+        del x3
+        print("[bench] three-level solve %.1f ms" % extra["f32_three_level"]["ms"], file=sys.stderr, flush=True)
 
     # Q-apply throughput (the stencil), timed with events on torch's stream
     qapply = {}

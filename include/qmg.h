@@ -87,9 +87,10 @@ typedef struct {
   int smoother;        /* 0: red-black SAP (nu_post sweeps); 1: GMRES smoothing, nu_post fixed
                           GMRES steps on the fine residual equation (Sec. 2's alternative) */
   int levels;          /* 2 (default), or 3: the coarse correction becomes coarse_maxiter steps of
-                          FGMRES on A_c (a K-cycle), right-preconditioned by the level-2 cycle
-                          (needs qmg_set_level3_vectors / qmg_setup_level3; always fixed steps) */
-  int l3_iters;        /* levels = 3: GMRES steps on the level-3 operator per level-2 cycle (20) */
+                          FGMRES on A_c (a K-cycle; a handful, e.g. 4), right-preconditioned by the
+                          level-2 cycle (needs qmg_set_level3_vectors / qmg_setup_level3; always
+                          fixed steps) */
+  int l3_iters;        /* levels = 3: GMRES steps on the level-3 operator per level-2 cycle (8) */
   int l2_smooth;       /* levels = 3: GMRES smoothing steps on level 2 per level-2 cycle (2) */
 } qmg_params;
 

@@ -176,7 +176,7 @@ qmg_params qmg_default_params(void) {
   p.q_form = 0;
   p.smoother = 0;
   p.levels = 2;
-  p.l3_iters = 20;
+  p.l3_iters = 8;
   p.l2_smooth = 2;
   return p;
 }
