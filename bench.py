@@ -65,10 +65,18 @@ def eigensolver_run(args, torch, qmg, random_links, seed_for, device_gaussian_sp
     ntv = 24
     W = lat.pack(device_gaussian_spinors(dims, ntv, seed_for(4, "W")))
     lat.setup_mg(W, ntv, setup_iters=6, smooth=4)
+    solve = {"mg_prec": "f32"}
+    if args.eig_levels == 3:
+        # inner solves with a third level (2^4 aggregates of blocks, 24 level-2 vectors)
+        k2, k3, s2 = (int(v) for v in (args.l3 or "4,8,2").split(","))
+        W2 = lat.level2_vectors_from(W, ntv)
+        lat.setup_level3(W2, ntv, (2, 2, 2, 2), setup_iters=3, smooth=s2, l3_iters=20)
+        del W2
+        solve.update(levels=3, coarse_maxiter=k2, l3_iters=k3, l2_smooth=s2)
     lat.autotune(None)
     t0v = lat.pack(device_gaussian_spinors(dims, 1, seed_for(4, "x")))
     X = lat.field(args.eig_nev)
-    prm = qmg.default_eig_params(block=args.eig_block, solve={"mg_prec": "f32"})
+    prm = qmg.default_eig_params(block=args.eig_block, solve=solve)
     torch.cuda.synchronize()
     print("[bench] eigensolver inputs and setup %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
     t1 = time.perf_counter()
@@ -86,7 +94,7 @@ def eigensolver_run(args, torch, qmg, random_links, seed_for, device_gaussian_sp
                         % ("x".join(map(str, dims)), m0, args.eig_nev),
             "seconds": sec, "status": st, "eigenpairs_per_s": len(lam) / sec,
             "outer_iters": stats["iters"], "inner_fgmres_iters": stats["inner_iters"],
-            "interp_updates": stats["interp_updates"], "block": args.eig_block,
+            "interp_updates": stats["interp_updates"], "block": args.eig_block, "levels": args.eig_levels,
             "max_residual": max(res) if res else None,
             "lambda_abs_range": [float(np.min(np.abs(lam))), float(np.max(np.abs(lam)))] if len(lam) else None}
 
@@ -321,6 +329,8 @@ def main():
                     help="lattice of the GD-lambdaAMG eigensolver measurement ('' to skip)")
     ap.add_argument("--eig-nev", type=int, default=20, help="eigenpairs in the eigensolver measurement")
     ap.add_argument("--eig-block", type=int, default=1, help="targets per outer step of the eigensolver")
+    ap.add_argument("--eig-levels", type=int, default=2, choices=[2, 3],
+                    help="multigrid levels of the eigensolver's inner solves")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="write the traffic summary from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of --mode kernels")
     args = ap.parse_args()

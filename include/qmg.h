@@ -295,7 +295,10 @@ qmg_eig_params qmg_default_eig_params(void);
  *           example the test vectors of qmg_setup_mg; may be NULL with n0 = 0);
  *   t0:     device, one internal F64 field, the first expansion vector.
  * Needs qmg_set_gauge (and, for a two-level inner solver and interpolation
- * updates, qmg_set_test_vectors or qmg_setup_mg).  Synchronises the stream.
+ * updates, qmg_set_test_vectors or qmg_setup_mg; for solve.levels = 3 also
+ * qmg_set_level3_vectors / qmg_setup_level3: every interpolation update then
+ * rebuilds the third level from P^H w_j of the first ntv2 new test vectors,
+ * same aggregates).  Synchronises the stream.
  * Once nev pairs are locked the iteration goes on while the smallest unlocked
  * |theta| lies below the largest locked |lambda| by more than its residual; a
  * pair that then converges replaces that largest one.  Needs m_min + block <=

@@ -681,6 +681,8 @@ qmg_status qmg_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const vo
       !(p.tol > 0) || p.maxiter < 1 || !(p.inner_tol > 0) || p.inner_maxiter < 1)
     return set_err(c, QMG_E_ARG, "eigensolve: bad parameters");
   QMG_TRY(check_prec(c, p.solve.mg_prec));
+  if (p.solve.use_coarse) QMG_TRY(need_mg(c));
+  QMG_TRY(check_levels(c, p.solve));
   hipSetDevice(c->device);
   return solver_eigensolve(c, nev, lambda, X, V0, n0, t0, &p, st, s);
 }

@@ -474,6 +474,21 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
       }
       st = build_mg(c, Wint, c->ntv, s);
       if (st != QMG_OK) return st;
+      if (ip.use_coarse && ip.levels == 3) {
+        // the third level follows the new P: its level-2 test vectors are
+        // P^H w_j of the first ntv2 new test vectors (same aggregates)
+        const int ntv2 = c->l3.ntv2;
+        const int b2[4] = {c->l3.block2[0], c->l3.block2[1], c->l3.block2[2], c->l3.block2[3]};
+        const size_t cb = coarse_elems(c) * 16;
+        void* W2 = ws_get(c, "eg_w2", cb * ntv2);
+        if (!W2) return set_err(c, QMG_E_NOMEM, "out of device memory (level-3 update)");
+        for (int k = 0; k < ntv2; ++k) {
+          hipError_t e = launch_restrict(c, QMG_F64, (char*)W2 + k * cb, fld(Wint, k), 1, s);
+          if (e != hipSuccess) return hip_err(c, e, "level-3 update");
+        }
+        st = build_l3(c, W2, ntv2, b2, s);
+        if (st != QMG_OK) return st;
+      }
       ++updates;
     }
     // correction equations (Q - theta_i) t_i = r_i for all targets, as one

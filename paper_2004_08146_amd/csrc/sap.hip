@@ -428,17 +428,15 @@ __global__ __launch_bounds__(256 * NS) void k_sap44(SapArgs<S> a) {
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc.s[s][c] = czero<float>();
+    // forward and backward hop of one direction together: their neighbour
+    // loads are in flight at the same time (a full unroll spills)
 #pragma unroll 1
-    for (int hop = 0; hop < 8; ++hop) {
-      switch (hop) {
-        case 0: res_hop44<0>(acc, x, a.U, Ul, nbr, b, l); break;
-        case 1: res_hop44<1>(acc, x, a.U, Ul, nbr, b, l); break;
-        case 2: res_hop44<2>(acc, x, a.U, Ul, nbr, b, l); break;
-        case 3: res_hop44<3>(acc, x, a.U, Ul, nbr, b, l); break;
-        case 4: res_hop44<4>(acc, x, a.U, Ul, nbr, b, l); break;
-        case 5: res_hop44<5>(acc, x, a.U, Ul, nbr, b, l); break;
-        case 6: res_hop44<6>(acc, x, a.U, Ul, nbr, b, l); break;
-        default: res_hop44<7>(acc, x, a.U, Ul, nbr, b, l); break;
+    for (int mu = 0; mu < 4; ++mu) {
+      switch (mu) {
+        case 0: res_hop44<0>(acc, x, a.U, Ul, nbr, b, l); res_hop44<1>(acc, x, a.U, Ul, nbr, b, l); break;
+        case 1: res_hop44<2>(acc, x, a.U, Ul, nbr, b, l); res_hop44<3>(acc, x, a.U, Ul, nbr, b, l); break;
+        case 2: res_hop44<4>(acc, x, a.U, Ul, nbr, b, l); res_hop44<5>(acc, x, a.U, Ul, nbr, b, l); break;
+        default: res_hop44<6>(acc, x, a.U, Ul, nbr, b, l); res_hop44<7>(acc, x, a.U, Ul, nbr, b, l); break;
       }
     }
     Spinor<float> xs = gl_spinor(x, b, l);

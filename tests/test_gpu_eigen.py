@@ -11,16 +11,23 @@ from synth import random_links, random_spinors, seed_for
 pytestmark = pytest.mark.gpu
 
 
-def _run(dims, block, m0, ntv, nev, mmin, mmax, cfg, update=1, seed=4, nblk=1):
+def _run(dims, block, m0, ntv, nev, mmin, mmax, cfg, update=1, seed=4, nblk=1, l3=None):
     qmg = need_gpu()
     U = random_links(dims, 0.5, seed_for(cfg, "U"))
     lat = qmg.Lattice(dims, block)
     lat.set_gauge(dev(U), m0, 1.0)
     W = lat.pack(dev(random_spinors(dims, ntv, seed_for(cfg, "W"))))
     lat.setup_mg(W, ntv, setup_iters=3, smooth=3)
+    solve = {}
+    if l3 is not None:
+        ntv2, block2 = l3
+        W2 = lat.level2_vectors_from(W, ntv2)
+        lat.setup_level3(W2, ntv2, block2, setup_iters=2, smooth=2, l3_iters=8)
+        solve = {"levels": 3, "coarse_maxiter": 3, "l3_iters": 8, "l2_smooth": 2}
     t0 = lat.pack(dev(random_spinors(dims, 1, seed_for(cfg, "x") + seed)))
     X = lat.field(nev)
-    prm = qmg.default_eig_params(m_min=mmin, m_max=mmax, maxiter=3000, update_interp=update, block=nblk)
+    prm = qmg.default_eig_params(m_min=mmin, m_max=mmax, maxiter=3000, update_interp=update, block=nblk,
+                                 solve=solve)
     st, lam, stats = lat.eigensolve(nev, X, t0, V0=W, n0=ntv, params=prm)
     return qmg, lat, U, st, lam, host(lat.unpack(X, nev)), stats
 
@@ -63,6 +70,29 @@ def test_eigensolve_8x4_pairs_valid(nblk):
     dims, m0 = (8, 8, 8, 8), -0.5
     qmg, lat, U, st, lam, X, stats = _run(dims, (4, 4, 4, 4), m0, 4, 8, 10, 20, 10, nblk=nblk)
     assert st == 0 and stats["converged"] == 8, stats
+    _check_pairs(U, m0, lam, X, 1.1e-8)
+    assert stats["interp_updates"] >= 1
+
+
+def test_eigensolve_three_level_inner_solves():
+    """Correction equations solved with three levels, the third level rebuilt after
+    every interpolation update (single-site level-2 aggregates on 4^4): the locked
+    eigenvalues are the dense oracle's; on 8^4 with 2^4 aggregates every pair is valid."""
+    case("eigensolve with three levels")
+    dims, m0 = (4, 4, 4, 4), -0.5
+    U = random_links(dims, 0.5, seed_for(9, "U"))
+    ref, _ = eigen.smallest_eigenpairs(U, m0, oclover.clover_term(U, 1.0), 40)
+    gaps = np.diff(np.abs(ref))
+    nev = 10 + int(np.argmax(gaps[9:20] > 1e-3))
+    qmg, lat, U2, st, lam, X, stats = _run(dims, (2, 2, 2, 2), m0, 8, nev, 10, 20, 9, l3=(4, (1, 1, 1, 1)))
+    assert st == 0 and stats["converged"] == nev, stats
+    assert np.allclose(np.sort(lam), np.sort(ref[:nev]), atol=1e-9, rtol=0)
+    _check_pairs(U, m0, lam, X, 1.1e-8)
+    assert stats["interp_updates"] >= 1
+    assert lat.level3_shape() == (16, 8)
+    dims = (8, 8, 8, 8)
+    qmg, lat, U, st, lam, X, stats = _run(dims, (2, 2, 2, 2), m0, 8, 10, 10, 20, 10, l3=(8, (2, 2, 2, 2)))
+    assert st == 0 and stats["converged"] == 10, stats
     _check_pairs(U, m0, lam, X, 1.1e-8)
     assert stats["interp_updates"] >= 1
 

@@ -179,3 +179,21 @@ def test_level3_arguments_and_state():
     with pytest.raises(qmg.QmgError) as e:
         lat.vcycle(lat.field(1), lat.pack(dev(random_spinors(dims, 1, 3))), [0.0], 1, qmg.default_params(levels=4))
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("prec,tol,qform", [("f64", 1e-10, 1), ("bf16", 5e-2, 0)])
+def test_vcycle3_qform_and_bf16(prec, tol, qform):
+    """Three-level V-cycle on Q - tau (every level in the Q form: Gamma5^cc D3 - tau on
+    level 3) and with BF16 storage of the fine and level-2 data (level 3 in FP32)."""
+    case("three-level vcycle 8^4 %s qform=%d" % (prec, qform))
+    dims, block, ntv, block2, ntv2 = CASES[0]
+    qmg, lat, op, W, two, W2, l3, order = _setup(*CASES[0])
+    three = mg3.ThreeLevel(op, W, block, W2, block2, k3=10, s2=2)
+    r = random_spinors(dims, 2, 53)
+    taus = [0.03, -0.07]
+    prm = qmg.default_params(levels=3, coarse_maxiter=3, l3_iters=10, l2_smooth=2, nu_post=2, n_mr=3,
+                             mg_prec=prec, q_form=qform)
+    z = host(lat.unpack(lat.vcycle(lat.field(2), lat.pack(dev(r)), taus, 2, prm), 2))
+    for k in range(2):
+        ref = three.vcycle(r[k], taus[k], 2, 3, 3, qform=bool(qform))
+        assert rel_err(z[k], ref) < tol, k
