@@ -2,10 +2,11 @@
 // out_k = (D_c - tau_k Gamma5^c) in_k.
 //
 // D_c couples each coarse site (lattice block) b to itself and to its 8
-// neighbouring blocks.  It is assembled column by column: prolong a unit
-// coarse vector, split D applied to it into the block-local part (diagonal
-// plus hops inside the block) and the 8 hop parts that leave the block, and
-// restrict each part with the receiving block's P.  Blocks are stored
+// neighbouring blocks.  It is assembled column by column, a batch of columns
+// at a time: prolong unit coarse vectors, split D applied to each into the
+// block-local part (diagonal plus hops inside the block) and the 8 hop parts
+// that leave the block, restrict all parts as one multi-rhs restriction (each
+// part with the receiving block's P) and scatter them into the blocks.  Blocks are stored
 // transposed, DcT[b][d][j][i] = D_c[b][d]_{ij}, d = 0 self, 1 + 2 mu for the
 // block at X + mu, 2 + 2 mu for X - mu (kept apart even when they coincide).
 // The apply kernels serve every coarse level: they take the level's neighbour
@@ -52,6 +53,19 @@ __global__ __launch_bounds__(256) void k_split(Geom g, double2* out9, const doub
     }
   }
   store_spinor(out9, g, b, l, loc0);
+}
+
+// DcT[b][d][c0 + kk][i] = part[kk * 9 + d][b][i]: restricted stencil parts of a
+// batch of kb unit columns into the transposed blocks of D_c
+__global__ __launch_bounds__(256) void k_scatter_dc(double2* DcT, const double2* part, int nb, int nc, int c0,
+                                                  int64_t total) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int i = (int)(idx % nc);
+  const int64_t t = idx / nc;
+  const int b = (int)(t % nb), n = (int)(t / nb);
+  const int kk = n / 9, d = n - 9 * kk;
+  DcT[(((int64_t)b * 9 + d) * nc + c0 + kk) * nc + i] = part[idx];
 }
 
 struct TauArr {
@@ -235,6 +249,14 @@ hipError_t launch_split_stencil(const qmg_ctx* c, void* out9, const void* in, hi
   hipLaunchKernelGGL(k_split, dim3((unsigned)((c->g.V + 255) / 256)), dim3(256), 0, s, c->g, (double2*)out9,
                      (const double2*)in, (const double2*)c->U[QMG_F64], (const double2*)c->Dg[QMG_F64],
                      c->m0 + 4.0, c->clover ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_dc(const qmg_ctx* c, void* Dc64, const void* part, int c0, int kb, hipStream_t s) {
+  const int nc = 2 * c->ntv;
+  const int64_t total = (int64_t)kb * 9 * c->g.nb * nc;
+  hipLaunchKernelGGL(k_scatter_dc, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (double2*)Dc64,
+                     (const double2*)part, c->g.nb, nc, c0, total);
   return hipGetLastError();
 }
 

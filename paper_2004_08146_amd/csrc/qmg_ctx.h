@@ -131,8 +131,8 @@ hipError_t launch_restrict(const qmg_ctx* c, int p, void* yc, const void* v, int
 hipError_t launch_prolong(const qmg_ctx* c, int p, void* v, const void* yc, int nrhs, hipStream_t s);
 // ---- coarse.hip
 hipError_t launch_split_stencil(const qmg_ctx* c, void* out9, const void* in, hipStream_t s);
-hipError_t launch_restrict_into_dc(const qmg_ctx* c, void* Dc64, const void* in9, int col,
-                                   hipStream_t s);
+// DcT[b][d][c0 + kk][:] = part[kk * 9 + d][b][:] for kk < kb (restricted parts, FP64)
+hipError_t launch_scatter_dc(const qmg_ctx* c, void* Dc64, const void* part, int c0, int kb, hipStream_t s);
 hipError_t launch_coarse_apply(const qmg_ctx* c, int p, void* out, const void* in, const double* tau,
                                int nrhs, hipStream_t s, int qform = 0);  // tau: host array
 // level-3 operator A3(tau) = D3 - tau Gamma5^cc on level-3 vectors of the coarse precision of p

@@ -552,16 +552,24 @@ qmg_status build_mg(qmg_ctx* c, const void* W, int ntv, hipStream_t s) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_err(c, e, "build P");
   if (hfail) return set_err(c, QMG_E_NUMERIC, "test vectors are locally rank deficient");
-  // D_c column by column
-  void* ycol = ws_get(c, "mg_ycol", coarse_elems(c) * 16);
-  void* pcol = ws_get(c, "mg_pcol", field_elems(c) * 16);
-  void* nine = ws_get(c, "mg_nine", field_elems(c) * 16 * 9);
-  if (!ycol || !pcol || !nine) return set_err(c, QMG_E_NOMEM, "out of device memory (D_c assembly)");
-  for (int col = 0; col < nc; ++col) {
-    e = launch_unit_coarse(ycol, g.nb, nc, col, s);
-    if (e == hipSuccess) e = launch_prolong(c, QMG_F64, pcol, ycol, 1, s);
-    if (e == hipSuccess) e = launch_split_stencil(c, nine, pcol, s);
-    if (e == hipSuccess) e = launch_restrict_into_dc(c, c->Dc[QMG_F64], nine, col, s);
+  // D_c column by column, kb columns per batch (workspace capped near 8 GiB):
+  // one multi-rhs prolongation and one multi-rhs restriction per batch read P
+  // once per 16 right-hand sides instead of once per part
+  const size_t fb = field_elems(c) * 16, cb = coarse_elems(c) * 16;
+  const int K = (int)std::max<size_t>(1, std::min<size_t>((size_t)nc, ((size_t)8 << 30) / (10 * fb)));
+  void* ycol = ws_get(c, "mg_ycol", cb * K);
+  void* pcol = ws_get(c, "mg_pcol", fb * K);
+  void* nine = ws_get(c, "mg_nine", fb * 9 * K);
+  void* part = ws_get(c, "mg_part", cb * 9 * K);
+  if (!ycol || !pcol || !nine || !part) return set_err(c, QMG_E_NOMEM, "out of device memory (D_c assembly)");
+  for (int c0 = 0; c0 < nc; c0 += K) {
+    const int kb = std::min(K, nc - c0);
+    for (int kk = 0; kk < kb && e == hipSuccess; ++kk) e = launch_unit_coarse((char*)ycol + kk * cb, g.nb, nc, c0 + kk, s);
+    if (e == hipSuccess) e = launch_prolong(c, QMG_F64, pcol, ycol, kb, s);
+    for (int kk = 0; kk < kb && e == hipSuccess; ++kk)
+      e = launch_split_stencil(c, (char*)nine + (size_t)kk * 9 * fb, (char*)pcol + (size_t)kk * fb, s);
+    if (e == hipSuccess) e = launch_restrict(c, QMG_F64, part, nine, 9 * kb, s);
+    if (e == hipSuccess) e = launch_scatter_dc(c, c->Dc[QMG_F64], part, c0, kb, s);
     if (e != hipSuccess) return hip_err(c, e, "assemble D_c");
   }
   for (int p = 1; p < 3; ++p) {
@@ -631,5 +639,6 @@ qmg_status solver_setup(qmg_ctx* c, void* W, int ntv, int iters, int smooth, int
   ws_release(c, "su_zero");
   ws_release(c, "su_new");
   ws_release(c, "mg_nine");
+  ws_release(c, "mg_pcol");
   return QMG_OK;
 }

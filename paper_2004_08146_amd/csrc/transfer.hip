@@ -398,19 +398,6 @@ hipError_t launch_build_P(const qmg_ctx* c, void* P64, const void* W, int ntv, i
   return hipGetLastError();
 }
 
-// Dc^T[b][d][col][:] = P_b^H in9[d]|_b for the 9 stencil parts d (column col of
-// every coarse block D_c[b][d], stored transposed)
-hipError_t launch_restrict_into_dc(const qmg_ctx* c, void* Dc64, const void* in9, int col, hipStream_t s) {
-  const int bs = 1 << c->g.bs_log;
-  const int nc = 2 * c->ntv;
-  size_t lds = sizeof(double) * 16 * std::max(bs, 4);
-  double2* base = (double2*)Dc64 + (int64_t)col * nc;
-  hipLaunchKernelGGL((k_restrict<double, double>), dim3(c->g.nb * 9), dim3(bs), lds, s, c->g, base,
-                     (const double2*)c->P[QMG_F64], (const double2*)in9, c->ntv, 9, (int64_t)field_elems(c),
-                     (int64_t)nc * nc, (int64_t)9 * nc * nc);
-  return hipGetLastError();
-}
-
 hipError_t launch_restrict(const qmg_ctx* c, int p, void* yc, const void* v, int nrhs, hipStream_t s) {
   if (p == QMG_F64) restrict_t<double>(c, yc, v, nrhs, s, p);
   else if (p == QMG_F32) restrict_t<float>(c, yc, v, nrhs, s, p);
