@@ -5,8 +5,9 @@
 // so Gamma5 P = P Gamma5^c (text before eq. (2.9)).  P is stored complex
 // [nb][2][ntv][6][bs]: column j of aggregate (b, h), entry (spin-in-half,
 // colour) d at site l.  Coarse vectors are [nrhs][nb][2*ntv], index h*ntv + j.
-// Columns of each aggregate are orthonormalised with modified Gram-Schmidt,
-// applied twice per column, in column order.
+// Columns of each aggregate are orthonormalised in column order, twice per
+// column, by Gram-Schmidt over chunks of eight earlier columns (modified
+// Gram-Schmidt in exact arithmetic).
 #include "qmg_ctx.h"
 #include "reduce.h"
 
@@ -16,6 +17,12 @@ QMG_HD int64_t pidx(const Geom& g, int ntv, int b, int h, int j, int d, int l) {
   return ((((int64_t)b * 2 + h) * ntv + j) * 6 + d) * ((int64_t)1 << g.bs_log) + l;
 }
 
+// Column j of both chirality halves: orthogonalised against columns 0..j-1
+// twice, eight columns at a time (the dot products of a chunk are reduced
+// together, then the chunk is subtracted), then normalised.  Equal to
+// modified Gram-Schmidt in exact arithmetic; one work-group reduction per
+// chunk instead of one per column pair.
+constexpr int kGsChunk = 8;
 __global__ __launch_bounds__(256) void k_build_P(Geom g, double2* P, const double2* W, int ntv, int* fail) {
   extern __shared__ double red[];
   const int b = blockIdx.x, l = threadIdx.x;
@@ -29,18 +36,30 @@ __global__ __launch_bounds__(256) void k_build_P(Geom g, double2* P, const doubl
       for (int d = 0; d < 6; ++d) n0[h] += norm2(v[h][d]);
     wg_sum<double, 2>(n0, red);
     for (int pass = 0; pass < 2; ++pass)
-      for (int i = 0; i < j; ++i) {
-        double cf[4] = {0, 0, 0, 0};
-        for (int h = 0; h < 2; ++h)
-          for (int d = 0; d < 6; ++d) {
-            cpx<double> t = cmul_conj(ldc(P, pidx(g, ntv, b, h, i, d, l)), v[h][d]);
-            cf[2 * h] += t.re;
-            cf[2 * h + 1] += t.im;
+      for (int i0 = 0; i0 < j; i0 += kGsChunk) {
+        // cf[4 t + 2 h + (0 re, 1 im)] = <P_{i0+t}, v> on chirality h
+        double cf[4 * kGsChunk];
+#pragma unroll
+        for (int t = 0; t < kGsChunk; ++t) {
+          const int i = i0 + t;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            cpx<double> a = czero<double>();
+            if (i < j)
+              for (int d = 0; d < 6; ++d) cfma_conj(a, ldc(P, pidx(g, ntv, b, h, i, d, l)), v[h][d]);
+            cf[4 * t + 2 * h] = a.re;
+            cf[4 * t + 2 * h + 1] = a.im;
           }
-        wg_sum<double, 4>(cf, red);
-        for (int h = 0; h < 2; ++h) {
-          cpx<double> c = {cf[2 * h], cf[2 * h + 1]};
-          for (int d = 0; d < 6; ++d) v[h][d] = v[h][d] - c * ldc(P, pidx(g, ntv, b, h, i, d, l));
+        }
+        wg_sum<double, 4 * kGsChunk>(cf, red);
+#pragma unroll
+        for (int t = 0; t < kGsChunk; ++t) {
+          const int i = i0 + t;
+          if (i < j)
+            for (int h = 0; h < 2; ++h) {
+              const cpx<double> c = {cf[4 * t + 2 * h], cf[4 * t + 2 * h + 1]};
+              for (int d = 0; d < 6; ++d) v[h][d] = v[h][d] - c * ldc(P, pidx(g, ntv, b, h, i, d, l));
+            }
         }
       }
     double n1[2] = {0, 0};
@@ -392,7 +411,8 @@ void prolong_t(const qmg_ctx* c, void* v, const void* yc, int nrhs, hipStream_t 
 
 hipError_t launch_build_P(const qmg_ctx* c, void* P64, const void* W, int ntv, int* d_fail, hipStream_t s) {
   const int bs = 1 << c->g.bs_log;
-  size_t lds = sizeof(double) * 4 * std::max(bs, 4);
+  // wg_sum scratch: 4 kGsChunk values per wave (per lane below 64 lanes)
+  size_t lds = sizeof(double) * 4 * kGsChunk * (bs >= 64 ? bs / 64 : bs);
   hipLaunchKernelGGL(k_build_P, dim3(c->g.nb), dim3(bs), lds, s, c->g, (double2*)P64, (const double2*)W, ntv,
                      d_fail);
   return hipGetLastError();
