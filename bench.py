@@ -35,7 +35,8 @@ TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_64x32x32x32_16rhs.json")
 # sources that define each profiled kernel: a change to any of them voids its counters
 KERNEL_SOURCES = {
     "sap_f32": ["paper_2004_08146_amd/csrc/sap.hip", "paper_2004_08146_amd/csrc/qmg_device.h"],
-    "stencil_f32": ["paper_2004_08146_amd/csrc/dslash.hip", "paper_2004_08146_amd/csrc/qmg_device.h"],
+    "stencil_f32": ["paper_2004_08146_amd/csrc/dslash.hip", "paper_2004_08146_amd/csrc/qmg_device.h",
+                    "paper_2004_08146_amd/csrc/tune.hip"],
 }
 KERNEL_NAMES = {"sap_f32": "k_sap44<float, true, 2, false>", "stencil_f32": "k_dslash"}
 

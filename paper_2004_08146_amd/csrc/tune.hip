@@ -102,40 +102,62 @@ qmg_status tune_run(qmg_ctx* c, const char* path) {
   js << "{\n";
   bool first = true;
   qmg_status st = QMG_OK;
-  for (int p = 0; p < 3 && st == QMG_OK; ++p)
-    for (int cls = 0; cls < 2 && st == QMG_OK; ++cls) {
-      const int n = cls == 0 ? 1 : 16;
-      const size_t bytes = field_elems(c) * cbytes(p) * n;
-      void* in = ws_get(c, "tune_in", bytes);
-      void* out = ws_get(c, "tune_out", bytes);
-      if (!in || !out) { st = set_err(c, QMG_E_NOMEM, "autotune: out of device memory"); break; }
-      if (launch_fill_zero(in, bytes, s) != hipSuccess) { st = set_err(c, QMG_E_HIP, "autotune: fill"); break; }
-      double best_ms = 1e30;
-      int best = c->tune.dslash[p][cls];
-      std::ostringstream times;
-      for (int v = 0; v < kNumDsVariants; ++v) {
-        if (v > 0 && !b44) break;
-        c->tune.force_variant = v;
-        hipError_t e = launch_dslash(c, p, out, in, tau.data(), n, 1, s);
-        if (e == hipSuccess) e = hipEventRecord(e0, s);
-        const int reps = 5;
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_dslash(c, p, out, in, tau.data(), n, 1, s);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) { st = hip_err(c, e, "autotune"); break; }
-        ms /= reps;
-        times << (v ? ", " : "") << ms;
-        if (ms < best_ms) { best_ms = ms; best = v; }
+  // stencil variants per (precision, 1 or 16 rhs), swept with and without the
+  // XCD-aware work-group mapping; the mapping (one setting for all stencil
+  // launches) with the smaller sum of best times is kept
+  int bestv[2][3][2];
+  double total[2] = {0.0, 0.0};
+  std::string tstr[2][3][2];
+  for (int rm = 1; rm >= 0 && st == QMG_OK; --rm) {
+    c->tune.dslash_xcd_remap = rm;
+    for (int p = 0; p < 3 && st == QMG_OK; ++p)
+      for (int cls = 0; cls < 2 && st == QMG_OK; ++cls) {
+        const int n = cls == 0 ? 1 : 16;
+        const size_t bytes = field_elems(c) * cbytes(p) * n;
+        void* in = ws_get(c, "tune_in", bytes);
+        void* out = ws_get(c, "tune_out", bytes);
+        if (!in || !out) { st = set_err(c, QMG_E_NOMEM, "autotune: out of device memory"); break; }
+        if (launch_fill_zero(in, bytes, s) != hipSuccess) { st = set_err(c, QMG_E_HIP, "autotune: fill"); break; }
+        double best_ms = 1e30;
+        int best = c->tune.dslash[p][cls];
+        std::ostringstream times;
+        for (int v = 0; v < kNumDsVariants; ++v) {
+          if (v > 0 && !b44) break;
+          c->tune.force_variant = v;
+          hipError_t e = launch_dslash(c, p, out, in, tau.data(), n, 1, s);
+          if (e == hipSuccess) e = hipEventRecord(e0, s);
+          const int reps = 5;
+          for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_dslash(c, p, out, in, tau.data(), n, 1, s);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) { st = hip_err(c, e, "autotune"); break; }
+          ms /= reps;
+          times << (v ? ", " : "") << ms;
+          if (ms < best_ms) { best_ms = ms; best = v; }
+        }
+        c->tune.force_variant = -1;
+        if (st != QMG_OK) break;
+        bestv[rm][p][cls] = best;
+        total[rm] += best_ms;
+        tstr[rm][p][cls] = times.str();
       }
-      c->tune.force_variant = -1;
-      if (st != QMG_OK) break;
-      c->tune.dslash[p][cls] = best;
-      js << (first ? "" : ",\n") << "  \"" << key << "|dslash|" << kPrecName[p] << "|" << cls << "\": " << best
-         << ",\n  \"" << key << "|dslash|" << kPrecName[p] << "|" << cls << "|ms\": [" << times.str() << "]";
-      first = false;
-    }
+  }
+  if (st == QMG_OK) {
+    const int rm = total[0] < total[1] ? 0 : 1;
+    c->tune.dslash_xcd_remap = rm;
+    for (int p = 0; p < 3; ++p)
+      for (int cls = 0; cls < 2; ++cls) {
+        c->tune.dslash[p][cls] = bestv[rm][p][cls];
+        js << (first ? "" : ",\n") << "  \"" << key << "|dslash|" << kPrecName[p] << "|" << cls << "\": "
+           << bestv[rm][p][cls] << ",\n  \"" << key << "|dslash|" << kPrecName[p] << "|" << cls << "|ms\": ["
+           << tstr[rm][p][cls] << "],\n  \"" << key << "|dslash|" << kPrecName[p] << "|" << cls
+           << "|ms_other_mapping\": [" << tstr[1 - rm][p][cls] << "]";
+        first = false;
+      }
+    js << ",\n  \"" << key << "|xcd_remap\": " << rm;
+  }
   // SAP kernel choice (FP32 arithmetic paths), one colour half-sweep on 16 rhs
   const int sap_default = c->tune.sap_variant;
   for (int p = 1; p < 3 && st == QMG_OK && c->sap_ok && b44; ++p) {
