@@ -253,6 +253,107 @@ def cpu_baseline(U, b0, m0, csw, tau, applies_per_rhs):
     }
 
 
+MFMA_JSON = os.path.join(ROOT, "profiles", "mfma_64x32x32x32_16rhs.json")
+MFMA_SOURCES = ["paper_2004_08146_amd/csrc/coarse.hip", "paper_2004_08146_amd/csrc/transfer.hip",
+                "paper_2004_08146_amd/csrc/qmg_device.h"]
+
+
+def mfma_util_for(kernel):
+    """rocprof MFMA utilisation (percent) of a kernel from the committed summary,
+    or None when the summary is missing or its sources have changed since."""
+    try:
+        with open(MFMA_JSON) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("sources_sha256_16") != sources_hash(MFMA_SOURCES):
+        return None
+    e = d.get("kernels", {}).get(kernel)
+    return e["mfma_util_pct"] if e else None
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}  # MI355X dense MFMA peaks (FP32, FP64)
+
+
+def mfma_mode(args, dims, torch, qmg, device_gaussian_spinors, random_links, seed_for):
+    """The multigrid's MFMA kernels at the solve's shape: coarse apply (FP32 and
+    FP64, 16 rhs), restriction and prolongation (FP32, 16 rhs), each timed with
+    HIP events; run under rocprofv3 --pmc MfmaUtil MfmaFlopsF32 MfmaFlopsF64 for
+    the matrix units' utilisation.  P comes from random test vectors (the work
+    does not depend on their values)."""
+    V = int(np.prod(dims))
+    nrhs = args.nrhs
+    U = random_links(dims, 0.5, seed_for(5, "U"))
+    lat = qmg.Lattice(dims, (4, 4, 4, 4))
+    lat.set_gauge(torch.from_numpy(U).cuda(), args.m0, 1.0)
+    del U
+    ntv = 24
+    W = lat.pack(device_gaussian_spinors(dims, ntv, seed_for(5, "W")))
+    lat.set_test_vectors(W, ntv)
+    del W
+    lat.autotune(args.tune_cache or os.path.join("/tmp", "qmg_tune_m_%d.json" % os.getpid()))
+    timer = EventTimer(torch)
+    taus = [0.001 * (2 * k - (nrhs - 1)) for k in range(nrhs)]
+    nb = V // 256
+    nc = 2 * ntv
+    out = {}
+    for prec in ("f32", "f64"):
+        yc = lat.coarse(nrhs, prec)
+        oc = lat.coarse(nrhs, prec)
+        ms = timer(lambda: lat.apply_coarse(oc, yc, taus, nrhs, prec), 10)
+        # one complex multiply-add = 4 real MFMA products = 8 flop
+        fl = 8.0 * 9 * nc * nc * nrhs * nb
+        out["coarse_apply_%s" % prec] = {"ms": ms, "mfma_flop": fl, "tflops": fl / ms / 1e9,
+                                         "frac_of_mfma_peak": fl / ms / 1e9 / MFMA_PEAK_TFLOPS[prec]}
+        del yc, oc
+    f = lat.field(nrhs, "f32")
+    yc = lat.coarse(nrhs, "f32")
+    fl = 8.0 * 12 * ntv * nrhs * V  # P^H v: 12 components x ntv columns per site and rhs
+    ms = timer(lambda: lat.restrict(yc, f, nrhs, "f32"), 10)
+    out["restrict_f32"] = {"ms": ms, "mfma_flop": fl, "tflops": fl / ms / 1e9,
+                           "frac_of_mfma_peak": fl / ms / 1e9 / MFMA_PEAK_TFLOPS["f32"]}
+    ms = timer(lambda: lat.prolong(f, yc, nrhs, "f32"), 10)
+    out["prolong_f32"] = {"ms": ms, "mfma_flop": fl, "tflops": fl / ms / 1e9,
+                          "frac_of_mfma_peak": fl / ms / 1e9 / MFMA_PEAK_TFLOPS["f32"]}
+    print(json.dumps({"mode": "mfma", "dims": list(dims), "nrhs": nrhs, "ntv": ntv, "kernels": out}))
+
+
+def summarize_mfma(pmc_dir, cmd):
+    """MFMA utilisation per kernel from a rocprofv3 --pmc MfmaUtil MfmaFlopsF32
+    MfmaFlopsF64 run of the mfma mode (the last 10 dispatches of each kernel:
+    the timed ones)."""
+    import csv
+    import glob
+    rows = {}
+    for f in glob.glob(os.path.join(pmc_dir, "*counter_collection.csv")):
+        for r in csv.DictReader(open(f)):
+            k = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+            rows.setdefault(k, {})[r["Counter_Name"]] = rows.get(k, {}).get(r["Counter_Name"], 0.0) + \
+                float(r["Counter_Value"])
+    disp = sorted(rows.items())
+
+    def short(n):
+        n = n.replace("(anonymous namespace)::", "")
+        if n.startswith("void "):
+            n = n[5:]
+        return n.split("(")[0]
+
+    out = {"command": cmd, "note": "MfmaUtil = 100 * SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE * SIMDs); "
+                                   "MfmaFlops = MFMA MOPS * 512; averages over the last 10 dispatches",
+           "kernels": {}}
+    for name in sorted({short(n) for (_, n), _ in disp}):
+        if "mfma" not in name:
+            continue
+        sel = [v for (_, n), v in disp if short(n) == name][-10:]
+        out["kernels"][name] = {
+            "dispatches": len(sel),
+            "mfma_util_pct": float(np.mean([v.get("MfmaUtil", 0.0) for v in sel])),
+            "mfma_flops_f32": float(np.mean([v.get("MfmaFlopsF32", 0.0) for v in sel])),
+            "mfma_flops_f64": float(np.mean([v.get("MfmaFlopsF64", 0.0) for v in sel]))}
+    out["sources_sha256_16"] = sources_hash(MFMA_SOURCES)
+    with open(MFMA_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def kernels_mode(args, dims, torch, qmg, unit_links):
     """A few launches of each hot kernel (memory traffic does not depend on the
     field values, so unit links are used) plus a plain 1 GiB device copy whose
@@ -325,7 +426,7 @@ def main():
                          "('' to skip)")
     ap.add_argument("--variant", type=int, default=None, help="kernels mode: pin this stencil variant")
     ap.add_argument("--remap", type=int, default=1, help="kernels mode: XCD-aware work-group mapping (with --variant)")
-    ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "kernels", "mfma"], default="solve",
                     help="kernels: only a few launches of the hot kernels and a 1 GiB copy (for counter runs)")
     ap.add_argument("--eig-dims", type=str, default="32,32,32,32",
                     help="lattice of the GD-lambdaAMG eigensolver measurement ('' to skip)")
@@ -336,6 +437,9 @@ def main():
     ap.add_argument("--eig-prec", type=str, default="bf16", choices=["f64", "f32", "bf16"],
                     help="V-cycle precision of the eigensolver's inner solves (they stop at a 0.1 "
                          "reduction, so BF16 storage suffices; FP64 outer FGMRES either way)")
+    ap.add_argument("--summarize-mfma", metavar="PMC_DIR", default=None,
+                    help="write the MFMA utilisation summary from a --pmc MfmaUtil MfmaFlopsF32 MfmaFlopsF64 "
+                         "run of --mode mfma")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="write the traffic summary from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of --mode kernels")
     args = ap.parse_args()
@@ -343,6 +447,12 @@ def main():
         cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc %s --output-format csv -d "
                "$GRAFT_REPO_ROOT/gpurun_out/pk_%s -o k -- python -u $GRAFT_REPO_ROOT/bench.py --mode kernels")
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], cmd)
+        return
+    if args.summarize_mfma:
+        cmd = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc MfmaUtil MfmaFlopsF32 MfmaFlopsF64 "
+               "--output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pm_mfma -o m -- python -u "
+               "$GRAFT_REPO_ROOT/bench.py --mode mfma")
+        summarize_mfma(args.summarize_mfma, cmd)
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -359,6 +469,8 @@ def main():
             args.m0 = float(json.load(fh)["m0"])
     if args.mode == "kernels":
         return kernels_mode(args, dims, torch, qmg, unit_links)
+    if args.mode == "mfma":
+        return mfma_mode(args, dims, torch, qmg, device_gaussian_spinors, random_links, seed_for)
     V = int(np.prod(dims))
     nrhs = args.nrhs
     csw, m0 = 1.0, args.m0
@@ -492,6 +604,19 @@ def main():
                         "traffic": traffic_for("stencil_f32"), "launch_ms": st["ms"],
                         "alg_bytes_per_launch": apply_bytes_per_site("f32", nrhs, True) * V}
 
+    # coarse apply on MFMA (FP32, 16 rhs): algorithmic MFMA rate against the FP32 MFMA peak,
+    # with the matrix units' busy fraction from the committed rocprof summary
+    ycs = lat.coarse(nrhs, "f32")
+    ocs = lat.coarse(nrhs, "f32")
+    cms = timer(lambda: lat.apply_coarse(ocs, ycs, taus, nrhs, "f32"), 10)
+    del ycs, ocs
+    cfl = 8.0 * 9 * (2 * ntv) ** 2 * nrhs * (V // 256)
+    roofline_coarse = {"bound": "mfma", "kernel": "coarse apply (D_c - tau Gamma5^c), FP32 MFMA, 16 rhs",
+                       "achieved": cfl / cms / 1e9, "peak": MFMA_PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                       "frac": cfl / cms / 1e9 / MFMA_PEAK_TFLOPS["f32"], "launch_ms": cms,
+                       "mfma_flop_per_launch": cfl,
+                       "mfma_util_pct": mfma_util_for("k_coarse_mfma<float, float, 3>")}
+
     eig = None
     if args.eig_dims:
         del lat
@@ -524,6 +649,7 @@ def main():
         "sap_sweep_f32": {"ms": sap_ms, "gbps": sap_bytes / sap_ms / 1e6, "hbm_frac": sap_bytes / sap_ms / 1e6 / HBM_PEAK_GBS},
         "roofline": roofline,
         "roofline_stencil": roofline_stencil,
+        "roofline_coarse": roofline_coarse,
         "eigensolver": eig,
         "autotune": tuning,
         "cpu_baseline": cpu,
