@@ -160,6 +160,41 @@ qmg_status tune_run(qmg_ctx* c, const char* path) {
       }
     js << ",\n  \"" << key << "|xcd_remap\": " << rm;
   }
+  // work order of the stencil (tiles of blocks) under the chosen mapping and
+  // variants: the sum over FP64 / FP32 with 1 and 16 rhs decides
+  if (st == QMG_OK && b44) {
+    const size_t bytes = field_elems(c) * cbytes(QMG_F64) * 16;
+    void* in = ws_get(c, "tune_in", bytes);
+    void* out = ws_get(c, "tune_out", bytes);
+    if (!in || !out) st = set_err(c, QMG_E_NOMEM, "autotune: out of device memory");
+    else if (launch_fill_zero(in, bytes, s) != hipSuccess) st = set_err(c, QMG_E_HIP, "autotune: fill");
+    double best_tot = 1e30;
+    int best_o = c->tune.ds_order;
+    std::ostringstream ot;
+    for (int o = 0; o < kNumDsOrders && st == QMG_OK; ++o) {
+      st = set_ds_order(c, o);
+      double tot = 0.0;
+      for (int p = 0; p < 2 && st == QMG_OK; ++p)
+        for (int cls = 0; cls < 2 && st == QMG_OK; ++cls) {
+          const int n = cls == 0 ? 1 : 16;
+          hipError_t e = launch_dslash(c, p, out, in, tau.data(), n, 1, s);
+          if (e == hipSuccess) e = hipEventRecord(e0, s);
+          for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch_dslash(c, p, out, in, tau.data(), n, 1, s);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess) st = hip_err(c, e, "autotune order");
+          tot += ms / 5;
+        }
+      ot << (o ? ", " : "") << tot;
+      if (st == QMG_OK && tot < best_tot * 0.99) { best_tot = tot; best_o = o; }
+    }
+    if (st == QMG_OK) st = set_ds_order(c, best_o);
+    if (st == QMG_OK)
+      js << ",\n  \"" << key << "|ds_order\": " << best_o << ",\n  \"" << key << "|ds_order|ms\": [" << ot.str()
+         << "]";
+  }
   // SAP kernel choice (FP32 arithmetic paths), one colour half-sweep on 16 rhs
   const int sap_default = c->tune.sap_variant;
   for (int p = 1; p < 3 && st == QMG_OK && c->sap_ok && b44; ++p) {
