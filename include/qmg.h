@@ -164,12 +164,20 @@ qmg_status qmg_sap_smooth(qmg_ctx* ctx, void* x, const void* f, const double* ta
  * Galerkin coarse operator D_c = P^H D P (Sec. 2) is assembled.
  * Returns QMG_E_NUMERIC for locally rank-deficient W. */
 qmg_status qmg_set_test_vectors(qmg_ctx* ctx, const void* W, int ntv, hipStream_t stream);
-/* Adaptive setup (reading of the paper's setup parameters): smooth W0 with
- * `smooth` SAP sweeps on D w = 0, then setup_iters-1 rounds of V-cycle
- * inverse iteration at tau = 0, rebuilding P and D_c each round.  W0 is
- * overwritten with the final test vectors (internal F64). */
+/* Adaptive setup (reading of the paper's setup parameters, Sec. 4 parameter
+ * table: 24 test vectors, 6 setup iterations, 4 smoothing steps): smooth W0
+ * with `smooth` FP64 SAP sweeps (n_mr minimal-residual steps per block) on
+ * D w = 0 and normalise, then setup_iters-1 rounds of inverse iteration
+ * w <- M(tau = 0) w, normalised, rebuilding P and D_c after each round; M is
+ * the two-level V-cycle (coarse GMRES to coarse_tol, at most coarse_maxiter
+ * steps, then `smooth` SAP sweeps) computed in precision `prec` (QMG_F64 for
+ * parity with an FP64 reference, QMG_F32 or QMG_BF16 for speed: the vectors
+ * only steer the multigrid's quality).  W0 (ntv internal F64 fields, device)
+ * is overwritten with the final test vectors.  QMG_E_NUMERIC when a vector
+ * vanishes or W is locally rank deficient.  Synchronous. */
 qmg_status qmg_setup_mg(qmg_ctx* ctx, void* W0, int ntv, int setup_iters, int smooth,
-                        int n_mr, int coarse_maxiter, double coarse_tol, hipStream_t stream);
+                        int n_mr, int coarse_maxiter, double coarse_tol, qmg_prec prec,
+                        hipStream_t stream);
 
 /* y_k = P^H v_k and v_k = P y_k (Sec. 2, R = P^H). */
 qmg_status qmg_restrict(qmg_ctx* ctx, void* yc, const void* v, int nrhs, qmg_prec p,

@@ -450,14 +450,15 @@ qmg_status qmg_set_test_vectors(qmg_ctx* c, const void* W, int ntv, hipStream_t 
 }
 
 qmg_status qmg_setup_mg(qmg_ctx* c, void* W0, int ntv, int setup_iters, int smooth, int n_mr, int coarse_maxiter,
-                        double coarse_tol, hipStream_t s) {
+                        double coarse_tol, qmg_prec prec, hipStream_t s) {
   if (!c) return QMG_E_ARG;
   QMG_TRY(need_gauge(c));
   QMG_TRY(need_sap(c));
+  QMG_TRY(check_prec(c, prec));
   if (!W0 || ntv < 1 || ntv > 32 || setup_iters < 1 || smooth < 0 || n_mr < 0 || coarse_maxiter < 1)
     return set_err(c, QMG_E_ARG, "setup_mg: bad arguments");
   hipSetDevice(c->device);
-  return solver_setup(c, W0, ntv, setup_iters, smooth, n_mr, coarse_maxiter, coarse_tol, s);
+  return solver_setup(c, W0, ntv, setup_iters, smooth, n_mr, coarse_maxiter, coarse_tol, prec, s);
 }
 
 qmg_status qmg_restrict(qmg_ctx* c, void* yc, const void* v, int nrhs, qmg_prec p, hipStream_t s) {

@@ -199,7 +199,7 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
                          const qmg_params* prm, qmg_stats* st, hipStream_t s);
 qmg_status build_mg(qmg_ctx* c, const void* W, int ntv, hipStream_t s);
 qmg_status solver_setup(qmg_ctx* c, void* W, int ntv, int iters, int smooth, int n_mr, int kc,
-                        double ctol, hipStream_t s);
+                        double ctol, int prec, hipStream_t s);
 qmg_status tune_run(qmg_ctx* c, const char* path);
 
 qmg_status set_err(qmg_ctx* c, qmg_status st, const std::string& msg);

@@ -588,7 +588,7 @@ qmg_status build_mg(qmg_ctx* c, const void* W, int ntv, hipStream_t s) {
 // smoothing steps): smooth random W on D w = 0 with SAP, then repeat
 // V-cycle inverse iteration (tau = 0), rebuilding P and D_c after each round.
 qmg_status solver_setup(qmg_ctx* c, void* W, int ntv, int iters, int smooth, int n_mr, int kc, double ctol,
-                        hipStream_t s) {
+                        int prec, hipStream_t s) {
   const int64_t n = (int64_t)field_elems(c);
   const size_t fb = (size_t)n * 16;
   Space sp{c, QMG_F64, n, ntv, s};
@@ -622,7 +622,7 @@ qmg_status solver_setup(qmg_ctx* c, void* W, int ntv, int iters, int smooth, int
   prm.n_mr = n_mr;
   prm.coarse_maxiter = kc;
   prm.coarse_tol = ctol;
-  prm.mg_prec = QMG_F32;
+  prm.mg_prec = (qmg_prec)prec;
   prm.use_coarse = 1;
   void* Wn = ws_get(c, "su_new", fb * ntv);
   if (!Wn) return set_err(c, QMG_E_NOMEM, "out of device memory (setup)");

@@ -82,7 +82,7 @@ _SIG = {
     "qmg_apply_A": ([_vp, _vp, _vp, _dp, _i, _i, _vp], _i),
     "qmg_sap_smooth": ([_vp, _vp, _vp, _dp, _i, _i, _i, _i, _vp], _i),
     "qmg_set_test_vectors": ([_vp, _vp, _i, _vp], _i),
-    "qmg_setup_mg": ([_vp, _vp, _i, _i, _i, _i, _i, _d, _vp], _i),
+    "qmg_setup_mg": ([_vp, _vp, _i, _i, _i, _i, _i, _d, _i, _vp], _i),
     "qmg_restrict": ([_vp, _vp, _vp, _i, _i, _vp], _i),
     "qmg_prolong": ([_vp, _vp, _vp, _i, _i, _vp], _i),
     "qmg_apply_coarse": ([_vp, _vp, _vp, _dp, _i, _i, _vp], _i),
@@ -268,9 +268,9 @@ class Lattice:
         self._check(_lib.qmg_set_test_vectors(self._h, _ptr(W), ntv, _stream()), "set_test_vectors")
         self.ntv = ntv
 
-    def setup_mg(self, W0, ntv, setup_iters=6, smooth=4, n_mr=3, coarse_maxiter=20, coarse_tol=0.5):
+    def setup_mg(self, W0, ntv, setup_iters=6, smooth=4, n_mr=3, coarse_maxiter=20, coarse_tol=0.5, prec="f32"):
         self._check(_lib.qmg_setup_mg(self._h, _ptr(W0), ntv, setup_iters, smooth, n_mr, coarse_maxiter,
-                                      float(coarse_tol), _stream()), "setup_mg")
+                                      float(coarse_tol), _PREC[prec], _stream()), "setup_mg")
         self.ntv = ntv
         return W0
 

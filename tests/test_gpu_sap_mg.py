@@ -46,24 +46,60 @@ def _force_sap(lat, tmp_path, dims, block, clover, v):
     lat.autotune(str(path))
 
 
+_SAP_REF = {}
+
+
+@pytest.mark.parametrize("nrhs", [2, 5, 16])
 @pytest.mark.parametrize("sapv", [0, 1, 2])
 @pytest.mark.parametrize("prec,tol", [("f32", 2e-5), ("bf16", 5e-2)])
-def test_sap_reduced_precision(prec, tol, sapv, tmp_path):
-    """FP32 / BF16-storage SAP (both kernels: generic and LDS-staged 4^4) on 2 rhs."""
-    case("sap 8^4 %s variant %d" % (prec, sapv))
+def test_sap_reduced_precision(prec, tol, sapv, nrhs, tmp_path):
+    """FP32 / BF16-storage SAP, all three kernels (generic; LDS-staged 4^4 with one or two
+    rhs per work-group), on 2, 5 and 16 rhs with distinct shifts: 16 rhs is the solve's batch
+    (eight passes of the two-slot kernel's rhs loop, alternating reduction buffers), 5 leaves
+    the second slot idle on the last pass.  Every rhs against the oracle."""
+    if sapv == 0 and nrhs != 2:
+        pytest.skip("the generic kernel takes one rhs per work-group: batch shape does not change its path")
+    case("sap 8^4 %s variant %d nrhs %d" % (prec, sapv, nrhs))
     dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
     qmg, lat, op = _op(dims, block)
     _force_sap(lat, tmp_path, dims, block, 1, sapv)
-    f = random_spinors(dims, 2, seed_for(2, "b"))
-    taus = [0.01, -0.15]
-    xg = lat.field(2, prec)
+    f = random_spinors(dims, nrhs, seed_for(2, "b") + nrhs)
+    taus = [-0.15 + 0.3 * k / max(1, nrhs - 1) for k in range(nrhs)]
+    xg = lat.field(nrhs, prec)
     fg = lat.pack(dev(f), prec)
-    lat.sap_smooth(xg, fg, taus, 2, nsweep=3, n_mr=3, prec=prec)
-    got = host(lat.unpack(xg, 2, prec))
-    fin = host(lat.unpack(fg, 2, prec))
-    for k in range(2):
-        ref = sap.sap(op, fin[k], np.zeros_like(f[0]), taus[k], block, 3, 3)
-        assert rel_err(got[k], ref) < tol
+    lat.sap_smooth(xg, fg, taus, nrhs, nsweep=3, n_mr=3, prec=prec)
+    got = host(lat.unpack(xg, nrhs, prec))
+    if (prec, nrhs) not in _SAP_REF:
+        fin = host(lat.unpack(fg, nrhs, prec))
+        _SAP_REF[(prec, nrhs)] = [sap.sap(op, fin[k], np.zeros_like(f[0]), taus[k], block, 3, 3)
+                                  for k in range(nrhs)]
+    errs = [rel_err(got[k], _SAP_REF[(prec, nrhs)][k]) for k in range(nrhs)]
+    print("max rel err %.2e" % max(errs), flush=True)
+    assert max(errs) < tol, errs
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 2e-3)])
+def test_setup_parity(prec, tol):
+    """qmg_setup_mg against the oracle's setup (smoothing on A_0 w = 0, then V-cycle inverse
+    iterations with interpolation rebuilds): 8^4, 8 test vectors, 4 setup iterations, 3
+    smoothing steps, coarse GMRES to 0.5 (at most 20 steps).  Both sides start from the same W.
+    FP64 V-cycles: the iteration is nonlinear (minimal-residual steps, a coarse GMRES whose
+    length depends on a tolerance test) and repeated four times, so rounding-order differences
+    grow from 1e-15 to about 1e-12; 1e-9 bounds them.  FP32 V-cycles: each round adds FP32
+    rounding of the smoother output (~1e-6 relative) that the next rounds carry along."""
+    case("setup parity 8^4 " + prec)
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    qmg, lat, op = _op(dims, block)
+    ntv = 8
+    W0 = random_test_vectors(dims, ntv, seed_for(2, "W"))
+    Wg = lat.pack(dev(W0))
+    lat.setup_mg(Wg, ntv, setup_iters=4, smooth=3, n_mr=3, coarse_maxiter=20, coarse_tol=0.5, prec=prec)
+    got = host(lat.unpack(Wg, ntv))
+    ref = mg.setup_test_vectors(op, list(W0), block, setup_iters=4, smooth=3, n_mr=3, coarse_iters=20,
+                                coarse_tol=0.5)
+    errs = [rel_err(got[j], ref[j]) for j in range(ntv)]
+    print("max rel err %.2e" % max(errs), flush=True)
+    assert max(errs) < tol, errs
 
 
 def _mg(dims, block, ntv=8, csw=1.0):

@@ -404,3 +404,99 @@ def test_qform_solve_same_solution():
     # Sec. 3.3: with approximate (MR) block solves multigrid for Q itself is far
     # slower than for the Gamma5-preconditioned form (here 10 vs 361 iterations)
     assert itq > 4 * ita, (ita, itq)
+
+
+class _FineOnly:
+    """Holds only the fine operator: the GMRES branch of TwoLevel.post_smooth
+    uses nothing else of the hierarchy."""
+
+    def __init__(self, op, block):
+        self.op = op
+        self.block = tuple(block)
+
+
+def _dense_A(op, tau, qform):
+    V = int(np.prod(op.dims))
+    A = dense.dense_D(op.U, op.m0, op.clover) - tau * dense.dense_gamma5(V)
+    return dense.dense_gamma5(V) @ A if qform else A
+
+
+def test_gmres_smoother_full_dimension_is_exact():
+    """GMRES smoothing (Sec. 2, the alternative to SAP) solves the residual equation
+    A e = r - A z; with as many steps as unknowns that solve is exact, so the smoothed
+    iterate is A^{-1} r whatever z it starts from (both operator forms).  A sign slip
+    in the residual (A z - r) or in the update (z - e) fails this."""
+    dims = (2, 2, 2, 2)
+    op = _op(dims, m0=0.5, csw=1.0)
+    tau = 0.1
+    r = random_spinors(dims, 1, 31)[0]
+    z0 = random_spinors(dims, 1, 32)[0]
+    for qform in (False, True):
+        xs = np.linalg.solve(_dense_A(op, tau, qform), r.reshape(-1))
+        for z_start in (np.zeros_like(z0), z0):
+            z = mg.TwoLevel.post_smooth(_FineOnly(op, (1, 1, 1, 1)), r, z_start, tau, 192, 3, qform,
+                                        "gmres")
+            assert np.abs(z.reshape(-1) - xs).max() < 1e-10 * np.abs(xs).max()
+
+
+def test_gmres_smoother_minimises_over_krylov_space():
+    """nu GMRES smoothing steps give z + e with e the element of the Krylov space
+    K_nu(A, s), s = r - A z, that minimises ||s - A e||: the same as a dense
+    least-squares solve over an explicitly built basis of that space."""
+    dims = (4, 4, 4, 2)
+    op = _op(dims, csw=1.0)
+    tau = 0.05
+    r = random_spinors(dims, 1, 33)[0]
+    z0 = random_spinors(dims, 1, 34)[0]
+    fine = _FineOnly(op, (2, 2, 2, 1))
+    for qform in (False, True):
+        A = _dense_A(op, tau, qform)
+        s = r.reshape(-1) - A @ z0.reshape(-1)
+        for nu in (1, 3, 6):
+            K = [s]
+            for _ in range(nu - 1):
+                K.append(A @ K[-1])
+            Qk, _ = np.linalg.qr(np.stack(K, axis=1))
+            c = np.linalg.lstsq(A @ Qk, s, rcond=None)[0]
+            ref = z0.reshape(-1) + Qk @ c
+            z = mg.TwoLevel.post_smooth(fine, r, z0, tau, nu, 3, qform, "gmres")
+            assert np.abs(z.reshape(-1) - ref).max() < 1e-10 * np.abs(ref).max()
+            # and the residual really went down
+            assert np.linalg.norm(r.reshape(-1) - A @ z.reshape(-1)) < np.linalg.norm(s)
+
+
+def test_setup_test_vectors_inverse_iteration():
+    """The adaptive-setup reading (Sec. 4 parameter table: test vectors, setup
+    iterations, smoothing steps): W is smoothed on A_0 w = 0 and then improved by
+    V-cycle inverse iteration at tau = 0.  The vectors come back normalised; their
+    mean ||A_0 w|| / ||w|| falls with every setup round and stays above the smallest
+    singular value of A_0; and the final interpolation represents the eigenvectors
+    of Q of smallest |lambda| better than random test vectors do (local coherence,
+    Sec. 3.1), which is what the setup is for."""
+    dims, block = (4, 4, 4, 2), (2, 2, 2, 1)
+    op = _op(dims, csw=1.0, m0=-0.5)
+    ntv = 6
+    W0 = [w / np.linalg.norm(w) for w in random_test_vectors(dims, ntv, seed_for(1, "W"))]
+    V = int(np.prod(dims))
+    smin = np.linalg.svd(_dense_A(op, 0.0, False), compute_uv=False)[-1]
+
+    def rq(ws):
+        return np.mean([np.linalg.norm(op.A(w, 0.0)) / np.linalg.norm(w) for w in ws])
+
+    prev = rq(W0)
+    W = W0
+    for iters in (1, 2, 3, 4):
+        W = mg.setup_test_vectors(op, W0, block, setup_iters=iters, smooth=2, n_mr=3, coarse_iters=20,
+                                  coarse_tol=0.5)
+        assert len(W) == ntv and all(abs(np.linalg.norm(w) - 1.0) < 1e-13 for w in W)
+        cur = rq(W)
+        assert smin <= cur < prev
+        prev = cur
+    lam, vec = np.linalg.eigh(dense.dense_Q(op.U, op.m0, op.clover))
+    low = [vec[:, i].reshape(dims + (4, 3)) for i in np.argsort(np.abs(lam))[:2 * ntv]]
+    P_setup = mg.build_P(W, block)
+    P_rand = mg.build_P(W0, block)
+    lc_setup = np.mean([mg.local_coherence(P_setup, v, block) for v in low])
+    lc_rand = np.mean([mg.local_coherence(P_rand, v, block) for v in low])
+    assert lc_setup > lc_rand + 0.1, (lc_setup, lc_rand)
+    assert V == 128
