@@ -135,6 +135,20 @@ qmg_status qmg_unpack(qmg_ctx* ctx, double* canon, const void* dev_internal, int
 qmg_status qmg_field_dot(qmg_ctx* ctx, double* result, const void* a, const void* b, int nrhs, qmg_prec p,
                          hipStream_t stream);
 
+/* As qmg_field_dot, for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): no device
+ * allocation of any kind.  The partial sums of the two-stage reduction and the
+ * results live in a fixed 16 MiB scratch array that the library keeps on every
+ * device it runs on until the process ends (its address is looked up once per
+ * device by qmg_create).  Limit: 2*nrhs + nrhs * ceil(12 V / 2048) * 2 <= 2^21
+ * doubles (V lattice sites): 64x32^3 takes any nrhs <= 64, 64^4 nrhs <= 21;
+ * larger requests return QMG_E_ARG.  Results are bitwise those of
+ * qmg_field_dot (same kernels, same summation order).  Every call on one
+ * device shares that device's scratch, so calls that overlap on one GPU (other
+ * host threads, other contexts, other streams) race; synchronises the stream. */
+qmg_status qmg_field_dot_noalloc(qmg_ctx* ctx, double* result, const void* a, const void* b, int nrhs,
+                                 qmg_prec p, hipStream_t stream);
+
 /* Gauge field (device, canonical complex128), bare mass m0 of eq. (2.5) and
  * clover coefficient csw.  Builds the clover term on the device (clover-leaf
  * field strength, traceless) and keeps F64/F32/BF16 copies.  Invalidates the

@@ -4,10 +4,35 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "qmg_ctx.h"
+
+// Scratch of qmg_field_dot_noalloc: the per-chunk partial sums of the
+// two-stage dot products followed by the final results.  One copy per device
+// (16 MiB), held until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device, never through the name.
+constexpr size_t kNoAllocDoubles = (size_t)1 << 21;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[256] = {};  // per device, filled once by the first qmg_create on that device
+
+// device address of this device's scratch (device already current); nullptr on failure
+double* scratch_address(int device) {
+  if (device < 0 || device >= 256) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    double* ptr = nullptr;
+    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+}  // namespace
 
 qmg_status set_err(qmg_ctx* c, qmg_status st, const std::string& msg) {
   if (c) c->err = msg;
@@ -287,6 +312,11 @@ qmg_status qmg_create(qmg_ctx** out, const int dims[4], const int block[4], int 
   g.nbr = c->d_nbr;
   g.bcoord = c->d_bcoord;
   g.lexord = c->d_lexord;
+  c->noalloc_scratch = scratch_address(device);
+  if (!c->noalloc_scratch) {
+    qmg_destroy(c);
+    return QMG_E_HIP;
+  }
   if (set_ds_order(c, c->tune.ds_order) != QMG_OK) {
     qmg_destroy(c);
     return QMG_E_HIP;
@@ -359,6 +389,26 @@ qmg_status qmg_field_dot(qmg_ctx* c, double* result, const void* a, const void* 
   QMG_TRY(hipchk(c, launch_multidot(p, d, a, 0, 1, b, n, n, nrhs, part, s), "field_dot"));
   QMG_TRY(hipchk(c, hipMemcpyAsync(result, d, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s), "field_dot D2H"));
   return hipchk(c, hipStreamSynchronize(s), "field_dot sync");
+}
+
+qmg_status qmg_field_dot_noalloc(qmg_ctx* c, double* result, const void* a, const void* b, int nrhs, qmg_prec p,
+                                 hipStream_t s) {
+  if (!c) return QMG_E_ARG;
+  QMG_TRY(check_prec(c, p));
+  QMG_TRY(check_nrhs(c, nrhs));
+  if (!result || !a || !b) return set_err(c, QMG_E_ARG, "field_dot_noalloc: null pointer");
+  const int64_t n = (int64_t)field_elems(c);
+  const size_t need = 2 * (size_t)nrhs + multidot_partial_doubles(n, 1, nrhs);
+  if (need > kNoAllocDoubles)
+    return set_err(c, QMG_E_ARG, "field_dot_noalloc: nrhs x lattice volume exceeds the fixed scratch (" +
+                                     std::to_string(need) + " > " + std::to_string(kNoAllocDoubles) + " doubles)");
+  hipSetDevice(c->device);
+  double* d = c->noalloc_scratch;
+  double* part = d + 2 * (size_t)nrhs;
+  QMG_TRY(hipchk(c, launch_multidot(p, d, a, 0, 1, b, n, n, nrhs, part, s), "field_dot_noalloc"));
+  QMG_TRY(hipchk(c, hipMemcpyAsync(result, d, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s),
+                 "field_dot_noalloc D2H"));
+  return hipchk(c, hipStreamSynchronize(s), "field_dot_noalloc sync");
 }
 
 qmg_status qmg_set_gauge(qmg_ctx* c, const double* U, double m0, double csw, hipStream_t s) {

@@ -92,6 +92,7 @@ struct qmg_ctx {
   std::map<std::string, hipGraphExec_t> graphs;  // captured V-cycles by (buffers, shifts, parameters)
   uint64_t ws_epoch = 0;                          // bumped whenever a workspace buffer moves
   hipStream_t cap_stream = nullptr;               // library stream used only to record graphs
+  double* noalloc_scratch = nullptr;              // device address of this device's no-allocation scratch
 };
 
 size_t field_elems(const qmg_ctx* c);   // complex elements in one fine field

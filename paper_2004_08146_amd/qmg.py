@@ -103,6 +103,7 @@ _SIG = {
     "qmg_apply_l3": ([_vp, _vp, _vp, _dp, _i, _i, _vp], _i),
     "qmg_level2_solve": ([_vp, _vp, _vp, _dp, _i, _i, _i, _i, _i, _vp], _i),
     "qmg_level3_shape": ([_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
+    "qmg_field_dot_noalloc": ([_vp, _dp, _vp, _vp, _i, _i, _vp], _i),
 }
 for _name, (_args, _res) in _SIG.items():
     _f = getattr(_lib, _name)
@@ -236,6 +237,13 @@ class Lattice:
         res = (ctypes.c_double * (2 * nrhs))()
         self._check(_lib.qmg_field_dot(self._h, res, _ptr(a), _ptr(b), nrhs, _PREC[prec], _stream()),
                     "field_dot")
+        return [complex(res[2 * k], res[2 * k + 1]) for k in range(nrhs)]
+
+    def field_dot_noalloc(self, a, b, nrhs=1, prec="f64"):
+        """field_dot without any device allocation (fixed library scratch)."""
+        res = (ctypes.c_double * (2 * nrhs))()
+        self._check(_lib.qmg_field_dot_noalloc(self._h, res, _ptr(a), _ptr(b), nrhs, _PREC[prec], _stream()),
+                    "field_dot_noalloc")
         return [complex(res[2 * k], res[2 * k + 1]) for k in range(nrhs)]
 
     # --------------------------------------------------------- operator --
