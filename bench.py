@@ -2,7 +2,7 @@
 
 Workload (config 5): 64x32^3 lattice, clover c_sw = 1.0, synthetic links
 exp(i*0.5*H), near-critical bare mass (m0 = -0.95 from tests/golden/
-m0_critical.json), 16 right-hand sides with shifts tau_k = 0.001*(2k - 15),
+m0_critical.json), 16 right-hand sides with shifts tau_k = 0.002*(2k - 15),
 two-level multigrid (4^4 aggregates, 24 test vectors, 6 setup iterations),
 FP64 FGMRES(6) to a 1e-10 true relative residual.
 
@@ -99,6 +99,50 @@ def eigensolver_run(args, torch, qmg, random_links, seed_for, device_gaussian_sp
             "inner_prec": args.eig_prec,
             "max_residual": max(res) if res else None,
             "lambda_abs_range": [float(np.min(np.abs(lam))), float(np.max(np.abs(lam)))] if len(lam) else None}
+
+
+def config4_run(args, torch, qmg, random_links, random_spinors, seed_for, device_gaussian_spinors, m0):
+    """The 32^4 mixed-precision workload: c_sw = 1, near-critical m0, two-level
+    multigrid (4^4 aggregates, 24 test vectors, 6 setup iterations), 8 shifts
+    tau_k = 0.005 (2k - 7) in one batch, FGMRES(6) to 1e-10 with the V-cycle in
+    FP32, BF16 storage or FP64 (graph mode, 20 coarse steps).  Each solve is run
+    once to record its graph, then timed."""
+    dims, nrhs = (32, 32, 32, 32), 8
+    t0 = time.time()
+    U = random_links(dims, 0.5, seed_for(4, "U"))
+    b = random_spinors(dims, nrhs, seed_for(4, "b"))
+    lat = qmg.Lattice(dims, (4, 4, 4, 4))
+    lat.set_gauge(torch.from_numpy(U).cuda(), m0, 1.0)
+    del U
+    bg = lat.pack(torch.from_numpy(b).cuda())
+    del b
+    W = lat.pack(device_gaussian_spinors(dims, 24, seed_for(4, "W")))
+    torch.cuda.synchronize()
+    t1 = time.time()
+    lat.setup_mg(W, 24, setup_iters=6, smooth=4, n_mr=3, coarse_maxiter=20, coarse_tol=0.5)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t1
+    del W
+    lat.autotune(os.path.join("/tmp", "qmg_tune_c4_%d.json" % os.getpid()))
+    taus = [0.005 * (2 * k - 7) for k in range(nrhs)]
+    out = {"workload": "32^4 clover (c_sw 1, m0 %.2f), 8 shifts tau_k = 0.005(2k - 7) in one batch, two-level MG, "
+                       "FGMRES(6) to 1e-10" % m0, "setup_s": setup_s, "solves": {}}
+    for prec in ("f32", "bf16", "f64"):
+        prm = qmg.default_params(mg_prec=prec, restart=6, maxiter=500, use_graph=1, coarse_maxiter=20)
+        x = lat.field(nrhs)
+        lat.solve_shifted(x, bg, taus, nrhs, prm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, stats = lat.solve_shifted(x, bg, taus, nrhs, prm)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t1)
+        out["solves"][prec] = {"ms": ms, "rhs_per_s": nrhs / (ms / 1000.0), "status": st,
+                               "iters": [s_["iters"] for s_ in stats],
+                               "max_true_relres": max(s_["true_relres"] for s_ in stats)}
+        del x
+    print("[bench] config-4 leg %.1f s: %s" % (time.time() - t0, json.dumps(out["solves"])), file=sys.stderr,
+          flush=True)
+    return out
 
 
 def sources_hash(names):
@@ -201,6 +245,30 @@ def sap_bytes_per_site(prec, nrhs, clover):
     return per_rhs * nrhs + shared
 
 
+def roofline_entry(kernel, flops, alg_bytes, launch_ms, flop_peak_tf, traffic):
+    """Roofline of one kernel launch, the bound chosen from the evidence: the
+    algorithmic arithmetic intensity (flops / algorithmic bytes) against the
+    ridge point of the published peaks (flop_peak_tf / 8 TB/s).  Below the ridge
+    HBM binds and `achieved` is algorithmic GB/s; above it the arithmetic peak
+    binds.  Both fractions are kept, plus the fraction of the issue ceiling
+    without packed FP32 (half the published FP32 vector peak)."""
+    ai = flops / alg_bytes
+    ridge = flop_peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
+    gbs = alg_bytes / launch_ms / 1e6
+    tfs = flops / launch_ms / 1e9
+    out = {"kernel": kernel, "launch_ms": launch_ms, "flops_per_launch": flops, "alg_bytes_per_launch": alg_bytes,
+           "arith_intensity_flop_per_byte": ai, "ridge_flop_per_byte": ridge,
+           "hbm_gbps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "tflops": tfs, "alu_frac": tfs / flop_peak_tf,
+           "frac_of_nonpacked_issue_peak": tfs / FP32_NONPACKED_TFLOPS,
+           "traffic": traffic}
+    if ai < ridge:
+        out.update({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS})
+    else:
+        out.update({"bound": "alu", "achieved": tfs, "peak": flop_peak_tf, "unit": "TFLOP/s",
+                    "frac": tfs / flop_peak_tf})
+    return out
+
+
 class EventTimer:
     def __init__(self, torch):
         self.torch = torch
@@ -219,38 +287,86 @@ class EventTimer:
         return s.elapsed_time(e) / reps
 
 
-def cpu_baseline(U, b0, m0, csw, tau, applies_per_rhs):
-    """The oracle (NumPy FP64) timed on one Q apply of one right-hand side on a
-    1/16 sub-volume of the workload's gauge field (32x16^3, same link
-    distribution), scaled to the full volume (the oracle's cost is linear in
-    the volume) and to right-hand sides per second with the number of
-    fine-operator applications the GPU solve needed per right-hand side."""
-    from threadpoolctl import threadpool_limits
+def cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"nproc": os.cpu_count(), "cpus_available": avail, "model": model}
 
-    from oracle import clover, dirac
-    sub = (slice(0, U.shape[0] // 2),) + (slice(0, U.shape[1] // 2),) * 3
-    Us = np.ascontiguousarray(U[sub])
-    scale = U[..., 0, 0, 0].size / Us[..., 0, 0, 0].size
-    nap = len(b0)
-    with threadpool_limits(1):
-        C = clover.clover_term(Us, csw)
-        t1 = time.perf_counter()
-        for k in range(nap):
-            dirac.apply_Q_shifted(Us, np.ascontiguousarray(b0[k][sub]), m0, tau, C)
-        t2 = time.perf_counter()
-    t_apply = (t2 - t1) / nap * scale
+
+def cpu_baseline(U, b0, m0, csw, tau, applies_per_rhs):
+    """The oracle (NumPy FP64) timed on this host.  The NumPy oracle is
+    single-threaded (its elementwise and einsum kernels run on one core), so
+    every figure is one core.
+
+    * The workload's own (Q - tau) apply on the whole lattice (64x32^3, clover),
+      one right-hand side, timed once after a warm-up apply on a 16^4 slice.
+      The oracle's clover term is built beforehand (untimed) on t-slabs in
+      worker processes (tests/oracle_slabs.py).  rhs/s = 1 / (apply time x the
+      number of fine-operator applications the GPU solve made per right-hand side:
+      an estimate; a full oracle solve at this size would take days).
+    * The same apply on a 16^4 lattice: median of 5 after a warm-up.
+    * A timed oracle solve: two-level multigrid FGMRES to 1e-10 on 8^4 (8 test
+      vectors, 2 setup rounds), 1 right-hand side, with the 16^4 workload's
+      m0 = -0.8 and tau = 0.01 -- at 16^4 the oracle needs minutes per V-cycle."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from oracle import clover, dirac, mg
+    from oracle.solve import solve_shifted
+    from oracle_slabs import default_procs, full_clover
+    from synth import random_links, random_spinors, random_test_vectors, seed_for
+
+    out = {"unit": "rhs/s", "cores": 1, "kind": "oracle", "threads": "1 (the NumPy oracle is single-threaded)"}
+    out.update(cpu_info())
+    t0 = time.perf_counter()
+    C = full_clover(U, csw)
+    clover_s = time.perf_counter() - t0
+    # warm-up on a 16^4 slice, then the whole lattice once
+    Us, Cs, xs = (np.ascontiguousarray(a[:16, :16, :16, :16]) for a in (U, C, b0[0]))
+    dirac.apply_Q_shifted(Us, xs, m0, tau, Cs)
+    t0 = time.perf_counter()
+    dirac.apply_Q_shifted(U, b0[0], m0, tau, C)
+    t_full = time.perf_counter() - t0
+    del C
     V = int(np.prod(U.shape[:4]))
-    return {
-        "value": 1.0 / (t_apply * applies_per_rhs),
-        "unit": "rhs/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": ("%d FP64 (Q - tau) applies (one per rhs) on a 1/16 sub-volume (32x16^3) of the clover "
-                   "workload, one thread, %.2f s in all, scaled x%d to %.1f s per full apply (the clover "
-                   "build is not timed), times %.0f fine-operator applications per rhs of the GPU solve"
-                   % (nap, t2 - t1, scale, t_apply, applies_per_rhs)),
-        "apply_gflops": FLOP_SITE * V / t_apply / 1e9,
-    }
+    out["value"] = 1.0 / (t_full * applies_per_rhs)
+    out["full_apply_s"] = t_full
+    out["full_apply_gflops"] = FLOP_SITE * V / t_full / 1e9
+    out["clover_build_s_untimed_slab_processes"] = clover_s
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        dirac.apply_Q_shifted(Us, xs, m0, tau, Cs)
+        ts.append(time.perf_counter() - t0)
+    out["apply_16x4_median_s"] = float(np.median(ts))
+    out["apply_16x4_gflops"] = FLOP_SITE * 16 ** 4 / float(np.median(ts)) / 1e9
+    dims8, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    U8 = random_links(dims8, 0.5, seed_for(4, "U"))
+    op = dirac.Operator(U8, -0.8, clover.clover_term(U8, csw))
+    t0 = time.perf_counter()
+    W = mg.setup_test_vectors(op, list(random_test_vectors(dims8, 8, seed_for(4, "W"))), block, setup_iters=2,
+                              smooth=3, n_mr=3, coarse_iters=20, coarse_tol=0.5)
+    h = mg.TwoLevel(op, W, block)
+    t1 = time.perf_counter()
+    b8 = random_spinors(dims8, 1, seed_for(4, "b"))[0]
+    x, it, hist = solve_shifted(op, b8, 0.01, block, mg=h, tol=1e-10, restart=8, maxiter=100)
+    t2 = time.perf_counter()
+    out["solve_8x4"] = {"setup_s": t1 - t0, "solve_s": t2 - t1, "fgmres_iters": it, "true_relres": hist[-1],
+                        "rhs_per_s": 1.0 / (t2 - t1)}
+    out["sample"] = ("the workload's FP64 (Q - tau) apply on the whole 64x32^3 clover lattice, one rhs, one thread: "
+                     "%.1f s (clover term built beforehand on t-slabs in %d processes, untimed); rhs/s = 1 / "
+                     "(apply time x %.0f fine-operator applications per rhs of the GPU solve). Also: 16^4 apply "
+                     "median of 5, and a whole oracle two-level solve on 8^4" % (t_full, default_procs(),
+                                                                              applies_per_rhs))
+    return out
 
 
 MFMA_JSON = os.path.join(ROOT, "profiles", "mfma_64x32x32x32_16rhs.json")
@@ -413,10 +529,11 @@ def main():
     ap.add_argument("--m0", type=float, default=None,
                     help="bare mass (default: the near-critical value in tests/golden/m0_critical.json)")
     ap.add_argument("--setup-iters", type=int, default=6)
-    ap.add_argument("--dtau", type=float, default=0.001, help="shift spacing: tau_k = dtau*(2k - nrhs + 1)")
+    ap.add_argument("--dtau", type=float, default=0.002, help="shift spacing: tau_k = dtau*(2k - nrhs + 1)")
     ap.add_argument("--maxiter", type=int, default=500)
     ap.add_argument("--restart", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-config4", action="store_true", help="skip the 32^4 8-shift mixed-precision leg")
     ap.add_argument("--quick", action="store_true", help="skip the extra FP64/BF16 solves")
     ap.add_argument("--tune-cache", type=str, default=None, help="autotuner JSON cache (default: fresh)")
     ap.add_argument("--graph", type=int, default=1, help="1: V-cycle replayed as a HIP graph (fixed coarse steps)")
@@ -590,19 +707,25 @@ def main():
     sap_bytes = sap_bytes_per_site("f32", nrhs, True) * V
     del xs, fs
     launch_ms = sap_ms / 2
-    sap_flops = sap_flops_per_site(3) * (V // 2) * nrhs
-    achieved = sap_flops / launch_ms / 1e9
-    roofline = {"bound": "alu", "kernel": "k_sap44<float, clover, 2 rhs slots>: one colour's half-sweep, 16 rhs",
-                "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic_for("sap_f32"),
-                "launch_ms": launch_ms, "flops_per_launch": sap_flops,
-                "flop_per_site_rhs": sap_flops_per_site(3),
-                "frac_of_nonpacked_issue_peak": achieved / FP32_NONPACKED_TFLOPS}
+    # the dominant kernel of the solve (about 40% of its kernel time): one colour's SAP half-sweep
+    roofline = roofline_entry("k_sap44<float, clover, 2 rhs slots>: one colour's SAP half-sweep, 16 rhs",
+                              sap_flops_per_site(3) * (V // 2) * nrhs, sap_bytes / 2, launch_ms,
+                              FP32_VECTOR_PEAK_TFLOPS, traffic_for("sap_f32"))
+    roofline["flop_per_site_rhs"] = sap_flops_per_site(3)
     st = qapply["f32_%drhs" % nrhs]
-    roofline_stencil = {"bound": "hbm", "kernel": "stencil (Q - tau), FP32, 16 rhs", "achieved": st["gbps"],
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": st["gbps"] / HBM_PEAK_GBS,
-                        "traffic": traffic_for("stencil_f32"), "launch_ms": st["ms"],
-                        "alg_bytes_per_launch": apply_bytes_per_site("f32", nrhs, True) * V}
+    roofline_stencil = roofline_entry("stencil (Q - tau), FP32, 16 rhs",
+                                      (FLOP_SITE + 552 + 48) * V * nrhs, apply_bytes_per_site("f32", nrhs, True) * V,
+                                      st["ms"], FP32_VECTOR_PEAK_TFLOPS, traffic_for("stencil_f32"))
+    # measured streaming-copy bandwidth: the practical ceiling of any HBM-bound kernel here
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    copy_ms = timer(lambda: qmg.stream_copy(dst, src), 10)
+    stream_copy = {"bytes_moved": 2 * (1 << 30), "ms": copy_ms, "gbps": 2 * (1 << 30) / copy_ms / 1e6,
+                   "frac_of_8TBs": 2 * (1 << 30) / copy_ms / 1e6 / HBM_PEAK_GBS,
+                   "kernel": "qmg_stream_copy (1 GiB read + 1 GiB written, 16 B per lane)"}
+    del src, dst
+    for r in (roofline, roofline_stencil):
+        r["frac_of_measured_copy"] = r["hbm_gbps"] / stream_copy["gbps"]
 
     # coarse apply on MFMA (FP32, 16 rhs): algorithmic MFMA rate against the FP32 MFMA peak,
     # with the matrix units' busy fraction from the committed rocprof summary
@@ -617,10 +740,14 @@ def main():
                        "mfma_flop_per_launch": cfl,
                        "mfma_util_pct": mfma_util_for("k_coarse_mfma<float, float, 3>")}
 
+    del lat
+    torch.cuda.empty_cache()
+    c4 = None
+    if not args.no_config4:
+        c4 = config4_run(args, torch, qmg, random_links, random_spinors, seed_for, device_gaussian_spinors, m0)
+        torch.cuda.empty_cache()
     eig = None
     if args.eig_dims:
-        del lat
-        torch.cuda.empty_cache()
         eig = eigensolver_run(args, torch, qmg, random_links, seed_for, device_gaussian_spinors, -0.8)
 
     # fine-operator applications per rhs: FGMRES apply + nu * (1 residual + n_MR block applies)
@@ -650,6 +777,8 @@ def main():
         "roofline": roofline,
         "roofline_stencil": roofline_stencil,
         "roofline_coarse": roofline_coarse,
+        "stream_copy": stream_copy,
+        "config4_32x32x32x32_8shifts": c4,
         "eigensolver": eig,
         "autotune": tuning,
         "cpu_baseline": cpu,

@@ -342,6 +342,13 @@ qmg_status qmg_hermitian_eig(int m, const double* a, double* w, double* z);
  * architecture and lattice shape (path may be NULL: no file). */
 qmg_status qmg_autotune(qmg_ctx* ctx, const char* cache_json_path);
 
+/* Bandwidth probe (not part of the method): copies `bytes` (a multiple of 16,
+ * both device pointers 16-byte aligned, regions not overlapping) from src to
+ * dst with a plain streaming kernel on `stream`, the reference against which
+ * the achieved bandwidth of the stencil kernels is read.  QMG_E_ARG on bad
+ * sizes or alignment, QMG_E_HIP if the launch fails.  Needs no context. */
+qmg_status qmg_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -738,6 +738,11 @@ qmg_status qmg_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const vo
   return solver_eigensolve(c, nev, lambda, X, V0, n0, t0, &p, st, s);
 }
 
+qmg_status qmg_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (!dst || !src || bytes % 16 != 0 || (uintptr_t)dst % 16 != 0 || (uintptr_t)src % 16 != 0) return QMG_E_ARG;
+  return launch_stream_copy(dst, src, bytes, s) == hipSuccess ? QMG_OK : QMG_E_HIP;
+}
+
 qmg_status qmg_autotune(qmg_ctx* c, const char* path) {
   if (!c) return QMG_E_ARG;
   QMG_TRY(need_gauge(c));

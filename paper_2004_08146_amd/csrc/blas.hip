@@ -165,6 +165,12 @@ __global__ __launch_bounds__(256) void k_gamma5(typename PT<S>::stor* y, const t
   }
 }
 
+// plain streaming copy, 16 B per lane per step (bandwidth probe)
+__global__ __launch_bounds__(256) void k_stream_copy(uint4* dst, const uint4* src, int64_t n) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) dst[i] = src[i];
+}
+
 __global__ void k_zero(uint32_t* p, int64_t n) {
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) p[i] = 0u;
@@ -296,6 +302,14 @@ hipError_t launch_gamma5_bs(int p, void* y, const void* x, int64_t n, int bs_log
     using P = typename PT<S>::stor;
     hipLaunchKernelGGL(k_gamma5<S>, dim3(ew_grid(n)), dim3(256), 0, s, (P*)y, (const P*)x, n, bs_log);
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 16);
+  // 4 work-groups per CU of 256 threads: enough loads in flight to saturate HBM
+  // with each lane streaming a long contiguous range of 16-B chunks
+  if (n > 0) hipLaunchKernelGGL(k_stream_copy, dim3(1024), dim3(256), 0, s, (uint4*)dst, (const uint4*)src, n);
   return hipGetLastError();
 }
 

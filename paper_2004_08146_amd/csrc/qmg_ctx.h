@@ -168,6 +168,7 @@ size_t multidot_partial_doubles(int64_t n, int J, int nrhs);
 hipError_t launch_multidot_shared(int p, double* dots, const void* V, int64_t vstride, int J, const void* w,
                                   int64_t wstride, int nw, int64_t n, double* partial, hipStream_t s);
 hipError_t launch_fill_zero(void* y, size_t bytes, hipStream_t s);
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // ---- force.hip
 hipError_t launch_unit_coarse(void* y, int nb, int nc, int col, hipStream_t s);
 hipError_t launch_force(const qmg_ctx* c, double* dU, double* dUb, const void* phi, const void* x,

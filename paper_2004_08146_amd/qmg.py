@@ -103,6 +103,7 @@ _SIG = {
     "qmg_apply_l3": ([_vp, _vp, _vp, _dp, _i, _i, _vp], _i),
     "qmg_level2_solve": ([_vp, _vp, _vp, _dp, _i, _i, _i, _i, _i, _vp], _i),
     "qmg_level3_shape": ([_vp, ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
+    "qmg_stream_copy": ([_vp, _vp, ctypes.c_size_t, _vp], _i),
     "qmg_field_dot_noalloc": ([_vp, _dp, _vp, _vp, _i, _i, _vp], _i),
 }
 for _name, (_args, _res) in _SIG.items():
@@ -151,6 +152,17 @@ def hermitian_eig(a):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def stream_copy(dst, src):
+    """Copy the bytes of device tensor src into dst with the library's streaming
+    kernel (a bandwidth probe)."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < n:
+        raise ValueError("stream_copy: destination too small")
+    st = _lib.qmg_stream_copy(_ptr(dst), _ptr(src), n, _stream())
+    if st != 0:
+        raise QmgError(st, "stream_copy")
 
 
 def _stream():
