@@ -36,3 +36,28 @@ def free_spectrum(dims, m0):
         e = np.sqrt(M * M + sum(np.sin(q) ** 2 for q in p))
         vals += [e] * 6 + [-e] * 6
     return np.sort(np.array(vals))
+
+
+def smallest_eigenpairs_sparse(U, m0, clover, k, extra=12):
+    """As smallest_eigenpairs, for lattices too large for a dense Q.
+
+    The eigenpairs of Q of smallest |lambda| are those of Q^2 of smallest
+    eigenvalue: Lanczos (scipy.sparse.linalg.eigsh) on Q^2, applied as two
+    products with the sparse Q of the site couplings, gives an orthonormal
+    basis of the span of the k + extra smallest; Q restricted to that span
+    (Rayleigh-Ritz, exact for an invariant subspace) is diagonalised densely and
+    the k pairs of smallest |lambda| are returned.  The margin of `extra`
+    vectors keeps a +-lambda pair from being cut at the boundary."""
+    import scipy.sparse.linalg as sla
+
+    dims = U.shape[:4]
+    Q = dense.sparse_Q(U, m0, clover)
+    Q2 = sla.LinearOperator(Q.shape, matvec=lambda v: Q @ (Q @ v), dtype=np.complex128)
+    m = k + extra
+    _, B = sla.eigsh(Q2, k=m, which="SA", ncv=max(2 * m + 20, 100), tol=1e-14, maxiter=200000)
+    B, _ = np.linalg.qr(B)
+    H = B.conj().T @ (Q @ B)
+    w, s = np.linalg.eigh(0.5 * (H + H.conj().T))
+    order = np.argsort(np.abs(w), kind="stable")[:k]
+    X = (B @ s[:, order]).T.reshape((k,) + tuple(dims) + (4, 3))
+    return w[order], X

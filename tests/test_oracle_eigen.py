@@ -54,3 +54,21 @@ def test_host_hermitian_eig_matches_lapack(m):
         w, z = qmg.hermitian_eig(b)
         assert np.allclose(w, np.sort(d.real), atol=1e-12)
         assert np.linalg.norm(b @ z - z * w) < 1e-12
+
+
+def test_sparse_lanczos_eigenpairs_match_dense():
+    """The Lanczos route for large lattices (eigsh on Q^2, then Rayleigh-Ritz of Q on
+    the span) against the dense definition on 4^4 with random links and clover:
+    the same eigenvalues, and pairs that are eigenpairs of the matrix-free oracle
+    operator, orthonormal."""
+    dims, m0 = (4, 4, 4, 4), -0.5
+    U = random_links(dims, 0.5, seed_for(9, "U"))
+    C = oclover.clover_term(U, 1.0)
+    ref, _ = eigen.smallest_eigenpairs(U, m0, C, 24)
+    lam, X = eigen.smallest_eigenpairs_sparse(U, m0, C, 20)
+    assert np.allclose(lam, ref[:20], atol=1e-11, rtol=0)
+    for k in range(20):
+        r = dirac.apply_Q(U, X[k], m0, C) - lam[k] * X[k]
+        assert np.linalg.norm(r) < 1e-10
+    G = X.reshape(20, -1).conj() @ X.reshape(20, -1).T
+    assert np.allclose(G, np.eye(20), atol=1e-11)
