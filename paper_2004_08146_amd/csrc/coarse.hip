@@ -2,22 +2,30 @@
 // out_k = (D_c - tau_k Gamma5^c) in_k.
 //
 // D_c couples each coarse site (lattice block) b to itself and to its 8
-// neighbouring blocks.  It is assembled column by column, a batch of columns
-// at a time: prolong unit coarse vectors, split D applied to each into the
-// block-local part (diagonal plus hops inside the block) and the 8 hop parts
-// that leave the block, restrict all parts as one multi-rhs restriction (each
-// part with the receiving block's P) and scatter them into the blocks.  Blocks are stored
-// transposed, DcT[b][d][j][i] = D_c[b][d]_{ij}, d = 0 self, 1 + 2 mu for the
-// block at X + mu, 2 + 2 mu for X - mu (kept apart even when they coincide).
-// The apply kernels serve every coarse level: they take the level's neighbour
-// table, site count and blocks.
+// neighbouring blocks.  Only the self block and the 4 forward blocks are
+// stored: D is Gamma5-Hermitian and Gamma5 P = P Gamma5^c (text before
+// eq. (2.9)), so Gamma5^c D_c Gamma5^c = D_c^H and, hop type by hop type, the
+// block coupling b to X - mu is Gamma5^c (the block coupling X - mu to b)^H
+// Gamma5^c.  The apply kernels rebuild those backward blocks on the fly.
+// D_c is assembled column by column, a batch of columns at a time: prolong
+// unit coarse vectors, split D applied to each into the block-local part
+// (diagonal plus hops inside the block) and the 4 forward hop parts that leave
+// the block, restrict all parts as one multi-rhs restriction (each part with
+// the receiving block's P) and scatter them into the blocks.  Blocks are
+// stored transposed, DcT[b][e][j][i] = D_c[b][e]_{ij}, e = 0 self, 1 + mu for
+// the block at X + mu (kept apart from the -mu coupling even when the two
+// neighbours coincide).  In the 9-entry stencil numbering used by the kernels,
+// d = 0 is self, d = 1 + 2 mu the block at X + mu, d = 2 + 2 mu the one at
+// X - mu.  The apply kernels serve every coarse level: they take the level's
+// neighbour table, site count and blocks.
 #include "qmg_ctx.h"
 
 namespace {
 
-// out9[0] = block-local part, out9[1+2mu] / out9[2+2mu] = forward / backward
-// hop leaving the block (zero where the hop stays inside)
-__global__ __launch_bounds__(256) void k_split(Geom g, double2* out9, const double2* in, const double2* U,
+// out5[0] = block-local part (diagonal, clover and the hops that stay inside
+// the block), out5[1 + mu] = forward hop leaving the block (zero where it stays
+// inside); the backward hops that leave the block are not needed
+__global__ __launch_bounds__(256) void k_split(Geom g, double2* out5, const double2* in, const double2* U,
                                                const double2* diag, double mass4, int clover) {
   int64_t site = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (site >= g.V) return;
@@ -43,19 +51,21 @@ __global__ __launch_bounds__(256) void k_split(Geom g, double2* out9, const doub
         for (int c = 0; c < 3; ++c) t.s[s][c] = czero<double>();
       accum_recon(t, w, mu, fwd);
       const bool inside = fwd ? (loc(g, l, mu) < g.msk[mu]) : (loc(g, l, mu) > 0);
-      Spinor<double> o;
       for (int s = 0; s < 4; ++s)
-        for (int c = 0; c < 3; ++c) {
-          o.s[s][c] = inside ? czero<double>() : (-0.5) * t.s[s][c];
+        for (int c = 0; c < 3; ++c)
           if (inside) loc0.s[s][c] = loc0.s[s][c] - 0.5 * t.s[s][c];
-        }
-      store_spinor(out9 + (1 + 2 * mu + dir) * fs, g, b, l, o);
+      if (fwd) {
+        Spinor<double> o;
+        for (int s = 0; s < 4; ++s)
+          for (int c = 0; c < 3; ++c) o.s[s][c] = inside ? czero<double>() : (-0.5) * t.s[s][c];
+        store_spinor(out5 + (1 + mu) * fs, g, b, l, o);
+      }
     }
   }
-  store_spinor(out9, g, b, l, loc0);
+  store_spinor(out5, g, b, l, loc0);
 }
 
-// DcT[b][d][c0 + kk][i] = part[kk * 9 + d][b][i]: restricted stencil parts of a
+// DcT[b][e][c0 + kk][i] = part[kk * 5 + e][b][i]: restricted stencil parts of a
 // batch of kb unit columns into the transposed blocks of D_c
 __global__ __launch_bounds__(256) void k_scatter_dc(double2* DcT, const double2* part, int nb, int nc, int c0,
                                                   int64_t total) {
@@ -64,8 +74,8 @@ __global__ __launch_bounds__(256) void k_scatter_dc(double2* DcT, const double2*
   const int i = (int)(idx % nc);
   const int64_t t = idx / nc;
   const int b = (int)(t % nb), n = (int)(t / nb);
-  const int kk = n / 9, d = n - 9 * kk;
-  DcT[(((int64_t)b * 9 + d) * nc + c0 + kk) * nc + i] = part[idx];
+  const int kk = n / 5, e = n - 5 * kk;
+  DcT[(((int64_t)b * 5 + e) * nc + c0 + kk) * nc + i] = part[idx];
 }
 
 struct TauArr {
@@ -92,14 +102,29 @@ __global__ __launch_bounds__(64) void k_coarse_apply(const int* nbr, int nb, typ
   cpx<R> acc[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) acc[t] = czero<R>();
-  const auto* Db = DcT + (int64_t)b * 9 * nc * nc;
-  for (int d = 0; d < 9; ++d)
-    for (int j = 0; j < nc; ++j) {
-      cpx<R> a = ldcv<R>(Db, ((int64_t)d * nc + j) * nc + i);
-#pragma unroll
-      for (int t = 0; t < T; ++t) acc[t] = acc[t] + a * xin[d][t][j];
-    }
   const R g5 = i < nc / 2 ? R(1) : R(-1);
+  for (int d = 0; d < 9; ++d) {
+    if (d == 0 || (d & 1)) {
+      // self (e = 0) or forward block e = 1 + mu of this site: row j of the transposed block
+      const auto* Dd = DcT + ((int64_t)b * 5 + (d + 1) / 2) * nc * nc;
+      for (int j = 0; j < nc; ++j) {
+        const cpx<R> a = ldcv<R>(Dd, (int64_t)j * nc + i);
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[t] = acc[t] + a * xin[d][t][j];
+      }
+    } else {
+      // backward block: D_c[b][X - mu]_{ij} = g_i g_j conj(F_{ji}), F the forward block of
+      // the site at X - mu, whose transposed storage holds F_{ji} at i * nc + j
+      const auto* Fd = DcT + ((int64_t)nbr[b * 8 + d - 1] * 5 + d / 2) * nc * nc + (int64_t)i * nc;
+      for (int j = 0; j < nc; ++j) {
+        const cpx<R> f = ldcv<R>(Fd, j);
+        const R gg = j < nc / 2 ? g5 : -g5;
+        const cpx<R> a = {gg * f.re, -gg * f.im};
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[t] = acc[t] + a * xin[d][t][j];
+      }
+    }
+  }
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int k = k0 + t;
@@ -125,6 +150,34 @@ template <typename R> struct MAcc;
 template <> struct MAcc<float> { using T = mf4; };
 template <> struct MAcc<double> { using T = md4; };
 
+// 4 consecutive complex entries (16-byte aligned) with wide loads, converted to R
+template <typename R>
+__device__ __forceinline__ void ld4c(const double2* p, cpx<R> (&f)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double2 v = p[q];
+    f[q] = {R(v.x), R(v.y)};
+  }
+}
+template <typename R>
+__device__ __forceinline__ void ld4c(const float2* p, cpx<R> (&f)[4]) {
+  const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+  f[0] = {R(a.x), R(a.y)};
+  f[1] = {R(a.z), R(a.w)};
+  f[2] = {R(b.x), R(b.y)};
+  f[3] = {R(b.z), R(b.w)};
+}
+template <typename R>
+__device__ __forceinline__ void ld4c(const uint32_t* p, cpx<R> (&f)[4]) {
+  const uint4 a = reinterpret_cast<const uint4*>(p)[0];
+  const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const cpx<float> v = cv(w[q]);
+    f[q] = {R(v.re), R(v.im)};
+  }
+}
+
 // row of output register r of lane l inside a 16x16 tile
 template <typename R> __device__ __forceinline__ int mrow(int l, int r);
 template <> __device__ __forceinline__ int mrow<float>(int l, int r) { return 4 * (l >> 4) + r; }
@@ -144,7 +197,8 @@ __global__ __launch_bounds__(64 * NT) void k_coarse_mfma(const int* nbr, int nb,
   const int t = tid >> 6, l = tid & 63;
   const int ln = l & 15, lk = l >> 4;
   AT acc_re = AT{0, 0, 0, 0}, acc_im = AT{0, 0, 0, 0};
-  const auto* Db = DcT + (int64_t)b * 9 * NC * NC;
+  // output row of this lane's A fragment
+  const int irow = 16 * t + ln;
 #pragma unroll 1
   for (int d = 0; d < 9; ++d) {
     const int nbk = d == 0 ? b : nbr[b * 8 + d - 1];
@@ -156,15 +210,41 @@ __global__ __launch_bounds__(64 * NT) void k_coarse_mfma(const int* nbr, int nb,
       if (d == 0) Bself[j][n] = v;
     }
     __syncthreads();
-    const auto* Dd = Db + (int64_t)d * NC * NC + 16 * t + ln;
+    if (d == 0 || (d & 1)) {
+      // self or forward block: A_{ij} at row j of the transposed block
+      const auto* Dd = DcT + ((int64_t)b * 5 + (d + 1) / 2) * NC * NC + irow;
 #pragma unroll 4
-    for (int j0 = 0; j0 < NC; j0 += 4) {
-      const cpx<R> bv = Bs[j0 + lk][ln];
-      const cpx<R> av = ldcv<R>(Dd, (int64_t)(j0 + lk) * NC);
-      acc_re = mfma(av.re, bv.re, acc_re);
-      acc_re = mfma(-av.im, bv.im, acc_re);
-      acc_im = mfma(av.re, bv.im, acc_im);
-      acc_im = mfma(av.im, bv.re, acc_im);
+      for (int j0 = 0; j0 < NC; j0 += 4) {
+        const cpx<R> bv = Bs[j0 + lk][ln];
+        const cpx<R> av = ldcv<R>(Dd, (int64_t)(j0 + lk) * NC);
+        acc_re = mfma(av.re, bv.re, acc_re);
+        acc_re = mfma(-av.im, bv.im, acc_re);
+        acc_im = mfma(av.re, bv.im, acc_im);
+        acc_im = mfma(av.im, bv.re, acc_im);
+      }
+    } else {
+      // backward block from the forward block F of the site at X - mu:
+      // A_{ij} = g_i g_j conj(F_{ji}), F_{ji} stored at i * NC + j, i.e. along row i.
+      // The contraction index is visited in a permuted order (A and B permuted
+      // alike): in each run of 16 columns, MFMA step s takes j = jb + 4 lk + s, so
+      // every lane reads its 4 consecutive entries of row i with one wide load
+      const auto* Fd = DcT + ((int64_t)nbk * 5 + d / 2) * NC * NC + (int64_t)irow * NC;
+      const R gi = irow < NC / 2 ? R(1) : R(-1);
+#pragma unroll
+      for (int jb = 0; jb < NC; jb += 16) {
+        cpx<R> f[4];
+        ld4c(Fd + jb + 4 * lk, f);
+        const R gg = (jb + 4 * lk < NC / 2) ? gi : -gi;  // the 4 columns share a chirality half
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const cpx<R> bv = Bs[jb + 4 * lk + q][ln];
+          const R are = gg * f[q].re, aim = -gg * f[q].im;
+          acc_re = mfma(are, bv.re, acc_re);
+          acc_re = mfma(-aim, bv.im, acc_re);
+          acc_im = mfma(are, bv.im, acc_im);
+          acc_im = mfma(aim, bv.re, acc_im);
+        }
+      }
     }
   }
   const int n = n0 + ln;
@@ -245,8 +325,8 @@ void capply_s(const qmg_ctx* c, const CLevel& lv, int p, void* out, const void* 
 
 }  // namespace
 
-hipError_t launch_split_stencil(const qmg_ctx* c, void* out9, const void* in, hipStream_t s) {
-  hipLaunchKernelGGL(k_split, dim3((unsigned)((c->g.V + 255) / 256)), dim3(256), 0, s, c->g, (double2*)out9,
+hipError_t launch_split_stencil(const qmg_ctx* c, void* out5, const void* in, hipStream_t s) {
+  hipLaunchKernelGGL(k_split, dim3((unsigned)((c->g.V + 255) / 256)), dim3(256), 0, s, c->g, (double2*)out5,
                      (const double2*)in, (const double2*)c->U[QMG_F64], (const double2*)c->Dg[QMG_F64],
                      c->m0 + 4.0, c->clover ? 1 : 0);
   return hipGetLastError();
@@ -254,7 +334,7 @@ hipError_t launch_split_stencil(const qmg_ctx* c, void* out9, const void* in, hi
 
 hipError_t launch_scatter_dc(const qmg_ctx* c, void* Dc64, const void* part, int c0, int kb, hipStream_t s) {
   const int nc = 2 * c->ntv;
-  const int64_t total = (int64_t)kb * 9 * c->g.nb * nc;
+  const int64_t total = (int64_t)kb * 5 * c->g.nb * nc;
   hipLaunchKernelGGL(k_scatter_dc, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (double2*)Dc64,
                      (const double2*)part, c->g.nb, nc, c0, total);
   return hipGetLastError();

@@ -100,11 +100,16 @@ __global__ __launch_bounds__(256) void k_build_P2(L3Tab t, double2* P2, const do
 
 // D3[a][e] = sum over the (q, d) with site b = sites[a][q] and stencil entry d
 // landing in block e of P2_b^H D_c[b][d] P2_{b'}, b' = nbr(b, d); one
-// work-group per (aggregate, block), T = D_c[b][d] P2_{b'} staged in LDS.
+// work-group per (aggregate, stored block), T = D_c[b][d] P2_{b'} staged in LDS.
+// Like D_c, D3 keeps the self block and the 4 forward blocks (stored index
+// blockIdx.y = 0 self, 1 + mu forward; stencil entry eblk = 0 or 1 + 2 mu): the
+// backward ones follow from Gamma5^cc D3 Gamma5^cc = D3^H.  D_c's backward
+// blocks are rebuilt from the forward block of the neighbour at X - mu:
+// D_c[b][2 + 2 mu]_{r,col} = g_r g_col conj(F_{col,r}).
 __global__ __launch_bounds__(256) void k_assemble_D3(L3Tab t, double2* D3T, const double2* DcT, const double2* P2) {
   extern __shared__ unsigned char smem_d3[];
   cpx<double>* T = reinterpret_cast<cpx<double>*>(smem_d3);  // [nc3][nc2]
-  const int a = blockIdx.x, eblk = blockIdx.y;
+  const int a = blockIdx.x, eout = blockIdx.y, eblk = eout == 0 ? 0 : 2 * eout - 1;
   const int ntv = t.ntv, ntv2 = t.ntv2, nc2 = 2 * ntv, nc3 = 2 * ntv2, L = t.bs2 * ntv;
   cpx<double> acc[kMaxOut];
 #pragma unroll
@@ -116,14 +121,26 @@ __global__ __launch_bounds__(256) void k_assemble_D3(L3Tab t, double2* D3T, cons
       if ((t.keep[b * 9 + d] ? 0 : d) != eblk) continue;
       const int bn = d == 0 ? b : t.nbr2[b * 8 + d - 1];
       const int an = t.agg[bn], qn = t.qloc[bn];
-      const double2* Dm = DcT + ((int64_t)b * 9 + d) * nc2 * nc2;  // D_c[b][d]_{r,col} at col * nc2 + r
+      const bool back = d > 0 && (d & 1) == 0;
+      // forward/self: D_c[b][d]_{r,col} at col * nc2 + r; backward: F_{col,r} of the
+      // forward block of bn at r * nc2 + col
+      const double2* Dm = back ? DcT + ((int64_t)bn * 5 + d / 2) * nc2 * nc2
+                               : DcT + ((int64_t)b * 5 + (d + 1) / 2) * nc2 * nc2;
       __syncthreads();
       for (int idx = threadIdx.x; idx < nc2 * nc3; idx += 256) {
         const int r = idx % nc2, cc = idx / nc2;
         const int hn = cc / ntv2, jn = cc - hn * ntv2;
         const double2* Pn = P2 + (((int64_t)an * 2 + hn) * L + (int64_t)qn * ntv) * ntv2 + jn;
         cpx<double> s = czero<double>();
-        for (int i2 = 0; i2 < ntv; ++i2) cfma(s, ldc(Dm, (int64_t)(hn * ntv + i2) * nc2 + r), ldc(Pn, (int64_t)i2 * ntv2));
+        if (back) {
+          // g_r g_col with col = hn ntv + i2: the sign of col is that of hn
+          const double g = ((r < ntv) == (hn == 0)) ? 1.0 : -1.0;
+          for (int i2 = 0; i2 < ntv; ++i2)
+            cfma(s, g * conj(ldc(Dm, (int64_t)r * nc2 + hn * ntv + i2)), ldc(Pn, (int64_t)i2 * ntv2));
+        } else {
+          for (int i2 = 0; i2 < ntv; ++i2)
+            cfma(s, ldc(Dm, (int64_t)(hn * ntv + i2) * nc2 + r), ldc(Pn, (int64_t)i2 * ntv2));
+        }
         T[idx] = s;
       }
       __syncthreads();
@@ -144,7 +161,7 @@ __global__ __launch_bounds__(256) void k_assemble_D3(L3Tab t, double2* D3T, cons
 #pragma unroll
   for (int m = 0; m < kMaxOut; ++m) {
     const int o = threadIdx.x + 256 * m;
-    if (o < nc3 * nc3) stc(D3T, ((int64_t)a * 9 + eblk) * nc3 * nc3 + o, acc[m]);
+    if (o < nc3 * nc3) stc(D3T, ((int64_t)a * 5 + eout) * nc3 * nc3 + o, acc[m]);
   }
 }
 
@@ -272,7 +289,7 @@ qmg_status build_l3(qmg_ctx* c, const void* W2, int ntv2, const int block2[4], h
   }
   int* dtab = (int*)ws_get(c, "l3_tab", tab.size() * sizeof(int));
   const int nc3 = 2 * ntv2, L = bs2 * c->ntv;
-  const size_t pel = (size_t)n3 * 2 * L * ntv2, del = (size_t)n3 * 9 * nc3 * nc3;
+  const size_t pel = (size_t)n3 * 2 * L * ntv2, del = (size_t)n3 * 5 * nc3 * nc3;  // D3: self + 4 forward blocks
   for (int sp = 0; sp < 2; ++sp) {
     const int p = sp == 0 ? QMG_F64 : QMG_F32;
     l.P2[sp] = ws_get(c, "l3_P" + std::to_string(sp), pel * cbytes(p));
@@ -307,7 +324,7 @@ qmg_status build_l3(qmg_ctx* c, const void* W2, int ntv2, const int block2[4], h
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_err(c, e, "build P2");
   if (hfail) return set_err(c, QMG_E_NUMERIC, "level-2 test vectors are locally rank deficient");
-  hipLaunchKernelGGL(k_assemble_D3, dim3(n3, 9), dim3(256), (size_t)nc3 * 2 * c->ntv * sizeof(cpx<double>), s, t,
+  hipLaunchKernelGGL(k_assemble_D3, dim3(n3, 5), dim3(256), (size_t)nc3 * 2 * c->ntv * sizeof(cpx<double>), s, t,
                      (double2*)l.D3[0], (const double2*)c->Dc[QMG_F64], (const double2*)l.P2[0]);
   e = hipGetLastError();
   if (e == hipSuccess) e = launch_convert(l.P2[1], QMG_F32, l.P2[0], QMG_F64, (int64_t)pel, s);

@@ -400,117 +400,177 @@ static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* 
 }
 
 // ------------------------------------------------------------------ FGMRES --
+// Columns that have converged when a restart cycle ends are dropped from the
+// batch: the next cycles run on the unconverged columns only (gathered to the
+// front of library buffers; every column is an independent system, so its
+// arithmetic does not depend on which others share the batch), and each
+// column's x is written back to the caller's x when it leaves the batch.
 qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, int nrhs, const qmg_params* prm,
                          qmg_stats* stats, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   const int m = std::max(1, prm->restart);
-  Space sp{c, QMG_F64, (int64_t)field_elems(c), nrhs, s};
-  const size_t bb = sp.bbytes();
+  const int64_t n = (int64_t)field_elems(c);
+  const size_t fb = (size_t)n * 16;  // one FP64 field
+  const size_t bb = fb * nrhs;
   // the preconditioned directions Z are kept in the preconditioner's own
   // precision: the V-cycle output is exact there, so the FP64 products read it
   // unchanged and half (or a quarter) of the bytes
   const int zprec = prm->mg_prec;
-  const size_t zb = (size_t)sp.n * nrhs * cbytes(zprec);
+  const size_t zb_full = (size_t)n * nrhs * cbytes(zprec);
   void* V = ws_get(c, "fg_V", bb * (m + 1));
-  void* Z = ws_get(c, "fg_Z", zb * m);
-  auto zat = [&](int j) { return (void*)((char*)Z + (size_t)j * zb); };
+  void* Z = ws_get(c, "fg_Z", zb_full * m);
   void* f = ws_get(c, "fg_f", bb);
   void* r = ws_get(c, "fg_r", bb);
   if (!V || !Z || !f || !r) return set_err(c, QMG_E_NOMEM, "out of device memory (FGMRES)");
   // Gamma5-preconditioned form: (D - tau Gamma5) x = Gamma5 b; q_form: (Q - tau) x = b itself
   const int mode = prm->q_form ? 1 : 0;
   hipError_t e = prm->q_form ? hipMemcpyAsync(f, b, bb, hipMemcpyDeviceToDevice, s)
-                             : launch_gamma5_bs(QMG_F64, f, b, sp.n * nrhs, c->g.bs_log, s);
+                             : launch_gamma5_bs(QMG_F64, f, b, n * nrhs, c->g.bs_log, s);
   if (e == hipSuccess) e = launch_fill_zero(x, bb, s);
   if (e == hipSuccess) e = hipMemcpyAsync(r, f, bb, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return hip_err(c, e, "fgmres init");
-  std::vector<double> bnorm, beta;
-  qmg_status st = sp.norms(bnorm, b);
-  if (st != QMG_OK) return st;
+  std::vector<double> bnorm;
+  {
+    Space sp0{c, QMG_F64, n, nrhs, s};
+    qmg_status st = sp0.norms(bnorm, b);
+    if (st != QMG_OK) return st;
+  }
   for (int k = 0; k < nrhs; ++k)
     if (!std::isfinite(bnorm[k])) return set_err(c, QMG_E_NUMERIC, "non-finite right-hand side");
   std::vector<int> iters(nrhs, 0), restarts(nrhs, 0), cits(nrhs, 0);
-  std::vector<double> relres(nrhs, 0.0);
+  std::vector<double> relres(nrhs, 0.0), rnorm(nrhs, 0.0);
+  // the working batch: na columns, column i is the caller's column cols[i]
+  int na = nrhs;
+  std::vector<int> cols(nrhs);
+  for (int k = 0; k < nrhs; ++k) cols[k] = k;
+  std::vector<double> tw(tau, tau + nrhs);
+  void *xw = x, *fw = f, *rw = r;
+  auto col = [&](void* base, int i) { return (char*)base + (size_t)i * fb; };
   int total = 0;
+  qmg_status st = QMG_OK;
   while (true) {
-    st = sp.norms(beta, r);
+    Space sp{c, QMG_F64, n, na, s};
+    std::vector<double> beta;
+    st = sp.norms(beta, rw);
     if (st != QMG_OK) return st;
-    std::vector<char> act(nrhs);
-    bool any = false;
-    for (int k = 0; k < nrhs; ++k) {
-      if (!std::isfinite(beta[k])) return set_err(c, QMG_E_NUMERIC, "non-finite residual");
-      relres[k] = bnorm[k] > 0 ? beta[k] / bnorm[k] : 0.0;
-      act[k] = relres[k] > prm->tol;
-      any = any || act[k];
+    std::vector<char> act(na);
+    int nact = 0;
+    for (int i = 0; i < na; ++i) {
+      if (!std::isfinite(beta[i])) return set_err(c, QMG_E_NUMERIC, "non-finite residual");
+      const int k = cols[i];
+      rnorm[k] = beta[i];
+      relres[k] = bnorm[k] > 0 ? beta[i] / bnorm[k] : 0.0;
+      act[i] = relres[k] > prm->tol;
+      nact += act[i];
     }
-    if (!any || total >= prm->maxiter) break;
-    std::vector<cd> a(nrhs);
-    std::vector<Lsq> lsq(nrhs);
-    for (int k = 0; k < nrhs; ++k) {
-      a[k] = act[k] ? 1.0 / beta[k] : 0.0;
-      lsq[k].init(m, beta[k]);
-      if (act[k]) restarts[k] += 1;
+    if (nact == 0 || total >= prm->maxiter) break;
+    if (nact <= (3 * na) / 4) {
+      // drop the converged columns: their x goes home, the others move to the front
+      void* xa = ws_get(c, "fg_xa", bb);
+      void* fa = ws_get(c, "fg_fa", bb);
+      void* ra = ws_get(c, "fg_ra", bb);
+      if (!xa || !fa || !ra) return set_err(c, QMG_E_NOMEM, "out of device memory (FGMRES compaction)");
+      int j = 0;
+      std::vector<int> ncols;
+      std::vector<double> ntw;
+      for (int i = 0; i < na && e == hipSuccess; ++i) {
+        if (!act[i]) {
+          if (xw != x) e = hipMemcpyAsync(col(x, cols[i]), col(xw, i), fb, hipMemcpyDeviceToDevice, s);
+          continue;
+        }
+        // destination index j <= i: moving front to back in order never overwrites a pending column
+        if (xw != xa || j != i) {
+          e = hipMemcpyAsync(col(xa, j), col(xw, i), fb, hipMemcpyDeviceToDevice, s);
+          if (e == hipSuccess) e = hipMemcpyAsync(col(fa, j), col(fw, i), fb, hipMemcpyDeviceToDevice, s);
+          if (e == hipSuccess) e = hipMemcpyAsync(col(ra, j), col(rw, i), fb, hipMemcpyDeviceToDevice, s);
+        }
+        ncols.push_back(cols[i]);
+        ntw.push_back(tw[i]);
+        ++j;
+      }
+      if (e != hipSuccess) return hip_err(c, e, "fgmres compaction");
+      xw = xa;
+      fw = fa;
+      rw = ra;
+      cols = ncols;
+      tw = ntw;
+      na = j;
+      act.assign(na, 1);
+      sp.nrhs = na;
     }
-    st = sp.scale(sp.at(V, 0), r, a);
+    const size_t zb = (size_t)n * na * cbytes(zprec);
+    auto zat = [&](int jj) { return (void*)((char*)Z + (size_t)jj * zb); };
+    std::vector<cd> a(na);
+    std::vector<Lsq> lsq(na);
+    for (int i = 0; i < na; ++i) {
+      a[i] = act[i] ? 1.0 / rnorm[cols[i]] : 0.0;
+      lsq[i].init(m, rnorm[cols[i]]);
+      if (act[i]) restarts[cols[i]] += 1;
+    }
+    st = sp.scale(sp.at(V, 0), rw, a);
     if (st != QMG_OK) return st;
     // basis vectors after the first stay unnormalised (v_j = sig_j W_j): the
     // product A z_j is orthogonalised in place in the next basis slot, and the
     // preconditioner takes W_j itself (flexible GMRES allows any z_j)
-    std::vector<std::vector<double>> sig(nrhs, std::vector<double>(m + 1, 0.0));
-    for (int k = 0; k < nrhs; ++k) sig[k][0] = 1.0;
-    std::vector<int> kk(nrhs, 0);
-    for (int j = 0; j < m; ++j) {
+    std::vector<std::vector<double>> sig(na, std::vector<double>(m + 1, 0.0));
+    for (int i = 0; i < na; ++i) sig[i][0] = 1.0;
+    std::vector<int> kk(na, 0);
+    for (int jj = 0; jj < m; ++jj) {
       int ci = 0;
-      void* w = sp.at(V, j + 1);
-      st = solver_vcycle(c, zat(j), sp.at(V, j), tau, nrhs, prm, &ci, s, zprec);
+      void* w = sp.at(V, jj + 1);
+      st = solver_vcycle(c, zat(jj), sp.at(V, jj), tw.data(), na, prm, &ci, s, zprec);
       if (st != QMG_OK) return st;
-      e = launch_dslash_d_in(c, w, zat(j), zprec, tau, nrhs, s, mode);
+      e = launch_dslash_d_in(c, w, zat(jj), zprec, tw.data(), na, s, mode);
       if (e != hipSuccess) return hip_err(c, e, "apply");
       std::vector<std::vector<cd>> h;
-      st = sp.arnoldi(h, V, j, w, &sig);
+      st = sp.arnoldi(h, V, jj, w, &sig);
       if (st != QMG_OK) return st;
       bool all = true;
-      for (int k = 0; k < nrhs; ++k) {
-        if (!act[k]) { a[k] = 0.0; continue; }
-        double est = lsq[k].update(j, h[k]);
-        kk[k] = j + 1;
-        iters[k] += 1;
-        cits[k] += ci;
-        const double hn = h[k][j + 1].real();
-        if (hn == 0.0 || est <= prm->tol * bnorm[k]) act[k] = 0;
-        all = all && !act[k];
+      for (int i = 0; i < na; ++i) {
+        if (!act[i]) { a[i] = 0.0; continue; }
+        double est = lsq[i].update(jj, h[i]);
+        kk[i] = jj + 1;
+        iters[cols[i]] += 1;
+        cits[cols[i]] += ci;
+        const double hn = h[i][jj + 1].real();
+        if (hn == 0.0 || est <= prm->tol * bnorm[cols[i]]) act[i] = 0;
+        all = all && !act[i];
       }
       // converged right-hand sides are orthogonalised like the others, so their
       // vectors stay bounded; their coefficients are no longer used
-      for (int k = 0; k < nrhs; ++k) {
-        const double hn = h[k][j + 1].real();
-        sig[k][j + 1] = (hn > 0.0 && std::isfinite(hn)) ? 1.0 / hn : 0.0;
+      for (int i = 0; i < na; ++i) {
+        const double hn = h[i][jj + 1].real();
+        sig[i][jj + 1] = (hn > 0.0 && std::isfinite(hn)) ? 1.0 / hn : 0.0;
       }
       ++total;
-      if (all || j + 1 == m || total >= prm->maxiter) break;
+      if (all || jj + 1 == m || total >= prm->maxiter) break;
     }
     int J = 0;
-    for (int k = 0; k < nrhs; ++k) J = std::max(J, kk[k]);
+    for (int i = 0; i < na; ++i) J = std::max(J, kk[i]);
     if (J > 0) {
-      std::vector<cd> coef((size_t)J * nrhs, cd(0));
-      for (int k = 0; k < nrhs; ++k) {
-        if (kk[k] == 0) continue;
-        std::vector<cd> yk = lsq[k].solve(kk[k]);
-        for (int i = 0; i < kk[k]; ++i) {
-          if (!std::isfinite(yk[i].real()) || !std::isfinite(yk[i].imag()))
+      std::vector<cd> coef((size_t)J * na, cd(0));
+      for (int i = 0; i < na; ++i) {
+        if (kk[i] == 0) continue;
+        std::vector<cd> yk = lsq[i].solve(kk[i]);
+        for (int l = 0; l < kk[i]; ++l) {
+          if (!std::isfinite(yk[l].real()) || !std::isfinite(yk[l].imag()))
             return set_err(c, QMG_E_NUMERIC, "non-finite least-squares solution");
-          coef[(size_t)k * J + i] = yk[i];
+          coef[(size_t)i * J + l] = yk[l];
         }
       }
-      st = sp.axpy(x, Z, J, sp.vstride(), coef, zprec);
+      st = sp.axpy(xw, Z, J, sp.vstride(), coef, zprec);
       if (st != QMG_OK) return st;
     }
     // true residual r = Gamma5 b - A_tau x
-    e = launch_dslash(c, QMG_F64, r, x, tau, nrhs, mode, s);
-    if (e == hipSuccess) e = launch_xmy(QMG_F64, r, f, sp.n, sp.n, nrhs, s);
+    e = launch_dslash(c, QMG_F64, rw, xw, tw.data(), na, mode, s);
+    if (e == hipSuccess) e = launch_xmy(QMG_F64, rw, fw, n, n, na, s);
     if (e != hipSuccess) return hip_err(c, e, "residual");
   }
-  e = hipStreamSynchronize(s);
+  // columns still in a compacted batch go home
+  if (xw != x)
+    for (int i = 0; i < na && e == hipSuccess; ++i)
+      e = hipMemcpyAsync(col(x, cols[i]), col(xw, i), fb, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_err(c, e, "sync");
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   bool conv = true;
@@ -532,7 +592,7 @@ qmg_status build_mg(qmg_ctx* c, const void* W, int ntv, hipStream_t s) {
   const Geom& g = c->g;
   const int nc = 2 * ntv;
   const size_t pel = (size_t)g.nb * 2 * ntv * 6 * ((size_t)1 << g.bs_log);
-  const size_t del = (size_t)g.nb * 9 * nc * nc;
+  const size_t del = (size_t)g.nb * 5 * nc * nc;  // self + 4 forward blocks per coarse site
   c->have_mg = false;
   c->l3.ok = false;  // the third level is built on D_c
   c->ntv = ntv;
@@ -556,19 +616,19 @@ qmg_status build_mg(qmg_ctx* c, const void* W, int ntv, hipStream_t s) {
   // one multi-rhs prolongation and one multi-rhs restriction per batch read P
   // once per 16 right-hand sides instead of once per part
   const size_t fb = field_elems(c) * 16, cb = coarse_elems(c) * 16;
-  const int K = (int)std::max<size_t>(1, std::min<size_t>((size_t)nc, ((size_t)8 << 30) / (10 * fb)));
+  const int K = (int)std::max<size_t>(1, std::min<size_t>((size_t)nc, ((size_t)8 << 30) / (6 * fb)));
   void* ycol = ws_get(c, "mg_ycol", cb * K);
   void* pcol = ws_get(c, "mg_pcol", fb * K);
-  void* nine = ws_get(c, "mg_nine", fb * 9 * K);
-  void* part = ws_get(c, "mg_part", cb * 9 * K);
-  if (!ycol || !pcol || !nine || !part) return set_err(c, QMG_E_NOMEM, "out of device memory (D_c assembly)");
+  void* five = ws_get(c, "mg_five", fb * 5 * K);
+  void* part = ws_get(c, "mg_part", cb * 5 * K);
+  if (!ycol || !pcol || !five || !part) return set_err(c, QMG_E_NOMEM, "out of device memory (D_c assembly)");
   for (int c0 = 0; c0 < nc; c0 += K) {
     const int kb = std::min(K, nc - c0);
     for (int kk = 0; kk < kb && e == hipSuccess; ++kk) e = launch_unit_coarse((char*)ycol + kk * cb, g.nb, nc, c0 + kk, s);
     if (e == hipSuccess) e = launch_prolong(c, QMG_F64, pcol, ycol, kb, s);
     for (int kk = 0; kk < kb && e == hipSuccess; ++kk)
-      e = launch_split_stencil(c, (char*)nine + (size_t)kk * 9 * fb, (char*)pcol + (size_t)kk * fb, s);
-    if (e == hipSuccess) e = launch_restrict(c, QMG_F64, part, nine, 9 * kb, s);
+      e = launch_split_stencil(c, (char*)five + (size_t)kk * 5 * fb, (char*)pcol + (size_t)kk * fb, s);
+    if (e == hipSuccess) e = launch_restrict(c, QMG_F64, part, five, 5 * kb, s);
     if (e == hipSuccess) e = launch_scatter_dc(c, c->Dc[QMG_F64], part, c0, kb, s);
     if (e != hipSuccess) return hip_err(c, e, "assemble D_c");
   }
@@ -638,7 +698,7 @@ qmg_status solver_setup(qmg_ctx* c, void* W, int ntv, int iters, int smooth, int
   }
   ws_release(c, "su_zero");
   ws_release(c, "su_new");
-  ws_release(c, "mg_nine");
+  ws_release(c, "mg_five");
   ws_release(c, "mg_pcol");
   return QMG_OK;
 }

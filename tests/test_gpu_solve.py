@@ -133,3 +133,39 @@ def test_solve_full_size_sampled():
         assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
         # at those sites Q x reproduces b up to the solve tolerance
         assert np.abs(got - b[k][tuple(np.array(sites).T)]).max() <= 1e-6
+
+
+def test_solve_batch_compaction_writes_back_every_column():
+    """FGMRES drops the columns that have converged when a restart cycle ends (later cycles
+    run on the others only) and writes each column's x back to its own slot.  8 shifts
+    with short restart cycles, so columns leave the batch at different restarts: every
+    column meets the tolerance under the oracle's operator, and each takes the iterations
+    it takes when solved alone (within one: the alone solve runs the single-rhs kernels)."""
+    case("solve 8^4 batch compaction")
+    qmg = need_gpu()
+    dims = (8, 8, 8, 8)
+    U = random_links(dims, 0.5, seed_for(4, "U"))
+    m0, csw = -0.8, 1.0
+    lat = qmg.Lattice(dims, (4, 4, 4, 4))
+    lat.set_gauge(dev(U), m0, csw)
+    ntv = 12
+    W = lat.pack(dev(random_test_vectors(dims, ntv, seed_for(4, "W"))))
+    lat.setup_mg(W, ntv, setup_iters=3, smooth=3)
+    nrhs = 8
+    taus = [0.03 * (k - 3.5) for k in range(nrhs)]
+    b = random_spinors(dims, nrhs, seed_for(4, "b") + 7)
+    prm = qmg.default_params(mg_prec="f32", restart=3, maxiter=300)
+    x = lat.field(nrhs)
+    st, stats = lat.solve_shifted(x, lat.pack(dev(b)), taus, nrhs, prm)
+    assert st == 0
+    its = [s["iters"] for s in stats]
+    print("iterations", its, flush=True)
+    assert len(set(its)) > 1          # the columns did converge at different times
+    xs = host(lat.unpack(x, nrhs))
+    C = oclover.clover_term(U, csw)
+    for k in range(nrhs):
+        assert _true_relres_oracle(U, m0, C, xs[k], b[k], taus[k]) <= 1.5e-10, k
+    for k in (int(np.argmin(its)), int(np.argmax(its))):
+        x1 = lat.field(1)
+        st1, s1 = lat.solve_shifted(x1, lat.pack(dev(b[k:k + 1])), [taus[k]], 1, prm)
+        assert st1 == 0 and abs(s1[0]["iters"] - its[k]) <= 1, (k, s1[0]["iters"], its[k])
