@@ -77,7 +77,7 @@ def eigensolver_run(args, torch, qmg, random_links, seed_for, device_gaussian_sp
     lat.autotune(None)
     t0v = lat.pack(device_gaussian_spinors(dims, 1, seed_for(4, "x")))
     X = lat.field(args.eig_nev)
-    prm = qmg.default_eig_params(block=args.eig_block, solve=solve)
+    prm = qmg.default_eig_params(block=args.eig_block, solve=solve, both_signs=args.eig_both_signs)
     torch.cuda.synchronize()
     print("[bench] eigensolver inputs and setup %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
     t1 = time.perf_counter()
@@ -96,6 +96,7 @@ def eigensolver_run(args, torch, qmg, random_links, seed_for, device_gaussian_sp
             "seconds": sec, "status": st, "eigenpairs_per_s": len(lam) / sec,
             "outer_iters": stats["iters"], "inner_fgmres_iters": stats["inner_iters"],
             "interp_updates": stats["interp_updates"], "block": args.eig_block, "levels": args.eig_levels,
+            "both_signs": args.eig_both_signs, "negative_pairs": int(np.sum(np.asarray(lam) < 0)),
             "inner_prec": args.eig_prec,
             "max_residual": max(res) if res else None,
             "lambda_abs_range": [float(np.min(np.abs(lam))), float(np.max(np.abs(lam)))] if len(lam) else None}
@@ -549,6 +550,9 @@ def main():
                     help="lattice of the GD-lambdaAMG eigensolver measurement ('' to skip)")
     ap.add_argument("--eig-nev", type=int, default=20, help="eigenpairs in the eigensolver measurement")
     ap.add_argument("--eig-block", type=int, default=1, help="targets per outer step of the eigensolver")
+    ap.add_argument("--eig-both-signs", type=int, default=1, choices=[0, 1],
+                    help="1: each outer step targets the smallest unlocked pair of each sign (finds both signs); "
+                         "0: the single smallest |theta| target of the printed algorithm")
     ap.add_argument("--eig-levels", type=int, default=2, choices=[2, 3],
                     help="multigrid levels of the eigensolver's inner solves")
     ap.add_argument("--eig-prec", type=str, default="bf16", choices=["f64", "f32", "bf16"],

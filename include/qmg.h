@@ -212,6 +212,9 @@ qmg_status qmg_vcycle(qmg_ctx* ctx, void* z, const void* r, const double* tau, i
 /* Solve (Q - tau_k I) x_k = b_k for k < nrhs (internal F64 fields x, b) by
  * FGMRES on (D - tau_k Gamma5) x_k = Gamma5 b_k, x0 = 0, each right-hand side
  * with its own Krylov space; stats: host array of nrhs (may be NULL).
+ * Columns that have converged when a restart cycle ends leave the batch (when
+ * at most three quarters remain): later cycles run on the others only, in
+ * library buffers, and every column's x is written back to its own slot.
  * Returns QMG_NOT_CONVERGED if some column missed tol within maxiter. */
 qmg_status qmg_solve_shifted(qmg_ctx* ctx, void* x, const void* b, const double* tau, int nrhs,
                              const qmg_params* params, qmg_stats* stats, hipStream_t stream);
@@ -294,6 +297,17 @@ typedef struct {
                           expand the space (1: one target per step, as Alg. GD-lambdaAMG) */
   qmg_params solve;    /* inner solver settings (precision, smoother, coarse steps);
                           tol, maxiter and use_graph are overridden */
+  int extraction;      /* 0: harmonic Ritz pairs of the pencil (QV)^H (QV) s = theta (QV)^H V s
+                          (Sec. 3.2, the method's choice for the eigenvalues of smallest
+                          modulus); 1: Rayleigh-Ritz pairs V^H Q V s = theta s (the extraction
+                          of the paper's Ritz versus harmonic Ritz comparison, Sec. 4) */
+  int both_signs;      /* 0: one target per step, the unlocked pair of smallest |theta|, and
+                          thick restarts keep the m_min of smallest |theta| (Alg. GD-lambdaAMG as
+                          printed); 1: each step targets the `block` unlocked pairs of smallest
+                          |theta| of each sign (2 block correction equations, one batched solve)
+                          and restarts keep both signs alternately.  Needs m_min + 2 block <= m_max.
+                          On fields whose lowest eigenvalues form well separated clusters of each
+                          sign, 0 can lock the smallest pairs of one sign only; 1 finds both */
 } qmg_eig_params;
 
 typedef struct {

@@ -219,6 +219,8 @@ qmg_eig_params qmg_default_eig_params(void) {
   e.solve = qmg_default_params();
   e.solve.mg_prec = QMG_F32;
   e.solve.restart = 5;
+  e.extraction = 0;
+  e.both_signs = 0;
   return e;
 }
 
@@ -728,8 +730,10 @@ qmg_status qmg_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const vo
   const qmg_eig_params p = prm ? *prm : qmg_default_eig_params();
   if (nev < 1 || !lambda || !X || !t0 || n0 < 0 || (n0 > 0 && !V0))
     return set_err(c, QMG_E_ARG, "eigensolve: bad arguments");
-  if (p.m_max < 2 || p.m_min < 1 || p.block < 1 || p.block > 16 || p.m_min + p.block > p.m_max || n0 >= p.m_max ||
-      !(p.tol > 0) || p.maxiter < 1 || !(p.inner_tol > 0) || p.inner_maxiter < 1)
+  if (p.m_max < 2 || p.m_min < 1 || p.block < 1 || p.block > 16 || p.both_signs < 0 || p.both_signs > 1 ||
+      p.m_min + (p.both_signs ? 2 : 1) * p.block > p.m_max || n0 >= p.m_max ||
+      !(p.tol > 0) || p.maxiter < 1 || !(p.inner_tol > 0) || p.inner_maxiter < 1 || p.extraction < 0 ||
+      p.extraction > 1)
     return set_err(c, QMG_E_ARG, "eigensolve: bad parameters");
   QMG_TRY(check_prec(c, p.solve.mg_prec));
   if (p.solve.use_coarse) QMG_TRY(need_mg(c));

@@ -159,6 +159,26 @@ bool harmonic_ritz(int m, const std::vector<cd>& G, const std::vector<cd>& M, st
   return true;
 }
 
+// Rayleigh-Ritz pairs of Q on the orthonormal search space: V^H Q V = M^H (M = W^H V,
+// Hermitian in exact arithmetic), taken symmetrised; sorted by |theta|.
+void rayleigh_ritz(int m, const std::vector<cd>& M, std::vector<double>& theta, std::vector<std::vector<cd>>& S) {
+  std::vector<cd> H((size_t)m * m);
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) H[(size_t)j * m + i] = 0.5 * (std::conj(M[(size_t)i * m + j]) + M[(size_t)j * m + i]);
+  std::vector<double> w;
+  std::vector<cd> Y;
+  herm_eig(m, H, w, Y);
+  std::vector<int> idx(m);
+  for (int k = 0; k < m; ++k) idx[k] = k;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return std::abs(w[x]) < std::abs(w[y]); });
+  theta.clear();
+  S.clear();
+  for (int k : idx) {
+    theta.push_back(w[k]);
+    S.emplace_back(Y.begin() + (size_t)k * m, Y.begin() + (size_t)(k + 1) * m);
+  }
+}
+
 }  // namespace
 
 qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const void* V0, int n0, const void* t0,
@@ -167,15 +187,16 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
   const int64_t n = (int64_t)field_elems(c);
   const size_t fb = (size_t)n * 16;
   const int mmax = prm->m_max, mmin = prm->m_min, nblk = prm->block;
+  const int ntgt = prm->both_signs ? 2 * nblk : nblk;  // correction equations per outer step
   auto fld = [&](void* base, int j) { return (void*)((char*)base + (size_t)j * fb); };
   void* V = ws_get(c, "eg_V", fb * (mmax + 1));
   void* W = ws_get(c, "eg_W", fb * (mmax + 1));
   void* T = ws_get(c, "eg_T", fb * (mmax + 1));
   // per target of a block step: correction t, Ritz vector u, Q u, residual r
-  void* Tc = ws_get(c, "eg_t", fb * nblk);
-  void* U = ws_get(c, "eg_u", fb * nblk);
-  void* QU = ws_get(c, "eg_Qu", fb * nblk);
-  void* R = ws_get(c, "eg_r", fb * nblk);
+  void* Tc = ws_get(c, "eg_t", fb * ntgt);
+  void* U = ws_get(c, "eg_u", fb * ntgt);
+  void* QU = ws_get(c, "eg_Qu", fb * ntgt);
+  void* R = ws_get(c, "eg_r", fb * ntgt);
   const int nmax = std::max(std::max(mmax, nev), c->ntv) + 2;
   double* d_dots = (double*)ws_get(c, "eg_dots", sizeof(double) * 4 * nmax);
   double* d_part = (double*)ws_get(c, "eg_part", sizeof(double) * multidot_partial_doubles(n, nmax, 2));
@@ -293,6 +314,10 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
         g[(size_t)j * m + i] = G[(size_t)j * ld + i];
         mm[(size_t)j * m + i] = M[(size_t)j * ld + i];
       }
+    if (prm->extraction == 1) {
+      rayleigh_ritz(m, mm, th, S);
+      return QMG_OK;
+    }
     if (!harmonic_ritz(m, g, mm, th, S)) return set_err(c, QMG_E_NUMERIC, "W^H W is not positive definite");
     return QMG_OK;
   };
@@ -379,7 +404,7 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
   ip.use_graph = 0;  // every correction equation has its own shift
   int iters = 0, inner = 0, updates = 0;
   bool done = false;
-  std::vector<qmg_stats> ist(nblk);
+  std::vector<qmg_stats> ist(ntgt);
   // QMG_PROGRESS=1: one line on stderr every 25 outer iterations (long runs)
   const char* pe = std::getenv("QMG_PROGRESS");
   const bool progress = pe && pe[0] == '1';
@@ -409,8 +434,24 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
       st = pencil(th, S);
       if (st != QMG_OK) return st;
       cand.clear();
-      for (size_t k = 0; k < th.size() && (int)cand.size() < nblk; ++k)
-        if (!is_locked(S[k])) cand.push_back((int)k);
+      if (prm->both_signs) {
+        // the `block` unlocked pairs of smallest |theta| of each sign, interleaved
+        std::vector<int> pos, neg;
+        for (size_t k = 0; k < th.size(); ++k) {
+          if (is_locked(S[k])) continue;
+          std::vector<int>& side = th[k] >= 0 ? pos : neg;
+          if ((int)side.size() < nblk) side.push_back((int)k);
+        }
+        for (int q = 0; q < nblk; ++q) {
+          if (q < (int)pos.size()) cand.push_back(pos[q]);
+          if (q < (int)neg.size()) cand.push_back(neg[q]);
+        }
+        // smallest |theta| first (the verification test below looks at the first target)
+        std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) { return std::abs(th[a]) < std::abs(th[b]); });
+      } else {
+        for (size_t k = 0; k < th.size() && (int)cand.size() < nblk; ++k)
+          if (!is_locked(S[k])) cand.push_back((int)k);
+      }
       if (cand.empty()) return set_err(c, QMG_E_NUMERIC, "no unlocked harmonic Ritz pair");
       rns.assign(cand.size(), 0.0);
       bool relock = false;
@@ -504,9 +545,23 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
     if (m + nt > mmax) {
       st = pencil(th, S);
       if (st != QMG_OK) return st;
+      // the m_min unlocked pairs of smallest |theta| (with both_signs: alternately
+      // the smallest of each sign, so neither side's approximations are dropped)
+      std::vector<int> keep;
+      if (prm->both_signs) {
+        std::vector<int> pos, neg;
+        for (size_t k = 0; k < th.size(); ++k)
+          if (!is_locked(S[k])) (th[k] >= 0 ? pos : neg).push_back((int)k);
+        for (size_t q = 0; (int)keep.size() < mmin && (q < pos.size() || q < neg.size()); ++q) {
+          if (q < pos.size() && (int)keep.size() < mmin) keep.push_back(pos[q]);
+          if (q < neg.size() && (int)keep.size() < mmin) keep.push_back(neg[q]);
+        }
+      } else {
+        for (size_t k = 0; k < th.size() && (int)keep.size() < mmin; ++k)
+          if (!is_locked(S[k])) keep.push_back((int)k);
+      }
       int kept = 0;
-      for (size_t k = 0; k < th.size() && kept < mmin; ++k) {
-        if (is_locked(S[k])) continue;
+      for (int k : keep) {
         hipError_t e = launch_fill_zero(fld(T, kept), fb, s);
         if (e != hipSuccess) return hip_err(c, e, "zero");
         st = axpy(fld(T, kept), V, m, S[k]);

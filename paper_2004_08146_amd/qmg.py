@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
 class EigParams(ctypes.Structure):
     _fields_ = [("m_min", ctypes.c_int), ("m_max", ctypes.c_int), ("tol", ctypes.c_double),
                 ("maxiter", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxiter", ctypes.c_int),
-                ("update_interp", ctypes.c_int), ("block", ctypes.c_int), ("solve", Params)]
+                ("update_interp", ctypes.c_int), ("block", ctypes.c_int), ("solve", Params),
+                ("extraction", ctypes.c_int), ("both_signs", ctypes.c_int)]
 
 
 class EigStats(ctypes.Structure):
