@@ -150,34 +150,6 @@ template <typename R> struct MAcc;
 template <> struct MAcc<float> { using T = mf4; };
 template <> struct MAcc<double> { using T = md4; };
 
-// 4 consecutive complex entries (16-byte aligned) with wide loads, converted to R
-template <typename R>
-__device__ __forceinline__ void ld4c(const double2* p, cpx<R> (&f)[4]) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const double2 v = p[q];
-    f[q] = {R(v.x), R(v.y)};
-  }
-}
-template <typename R>
-__device__ __forceinline__ void ld4c(const float2* p, cpx<R> (&f)[4]) {
-  const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
-  f[0] = {R(a.x), R(a.y)};
-  f[1] = {R(a.z), R(a.w)};
-  f[2] = {R(b.x), R(b.y)};
-  f[3] = {R(b.z), R(b.w)};
-}
-template <typename R>
-__device__ __forceinline__ void ld4c(const uint32_t* p, cpx<R> (&f)[4]) {
-  const uint4 a = reinterpret_cast<const uint4*>(p)[0];
-  const uint32_t w[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const cpx<float> v = cv(w[q]);
-    f[q] = {R(v.re), R(v.im)};
-  }
-}
-
 // row of output register r of lane l inside a 16x16 tile
 template <typename R> __device__ __forceinline__ int mrow(int l, int r);
 template <> __device__ __forceinline__ int mrow<float>(int l, int r) { return 4 * (l >> 4) + r; }

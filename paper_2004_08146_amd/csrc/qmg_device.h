@@ -102,6 +102,35 @@ QMG_HD double2 vc(cpx<double> a, double2*) { return make_double2(a.re, a.im); }
 QMG_HD float2 vc(cpx<float> a, float2*) { return make_float2(a.re, a.im); }
 QMG_HD uint32_t vc(cpx<float> a, uint32_t*) { return f32_to_bf16_bits(a.re) | (f32_to_bf16_bits(a.im) << 16); }
 
+// 4 consecutive complex entries (16-byte aligned) with wide loads, converted to R
+template <typename R>
+__device__ __forceinline__ void ld4c(const double2* p, cpx<R> (&f)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double2 v = p[q];
+    f[q] = {R(v.x), R(v.y)};
+  }
+}
+template <typename R>
+__device__ __forceinline__ void ld4c(const float2* p, cpx<R> (&f)[4]) {
+  const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+  f[0] = {R(a.x), R(a.y)};
+  f[1] = {R(a.z), R(a.w)};
+  f[2] = {R(b.x), R(b.y)};
+  f[3] = {R(b.z), R(b.w)};
+}
+template <typename R>
+__device__ __forceinline__ void ld4c(const uint32_t* p, cpx<R> (&f)[4]) {
+  const uint4 a = reinterpret_cast<const uint4*>(p)[0];
+  const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const cpx<float> v = cv(w[q]);
+    f[q] = {R(v.re), R(v.im)};
+  }
+}
+
+
 // ------------------------------------------------------------------ layout --
 // Sites are grouped in blocks of B0 x B1 x B2 x B3 (powers of two), numbered
 // colour-major (all red blocks, then all black blocks).  A site is (b, l) with

@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void k_prolong_mr(Geom g, typename PT<S>::stor
 // ---- restriction on MFMA: per block and chirality h, Y_h (ntv x 16 rhs) =
 // P_h^H (ntv x K) V_h (K x 16), K = 6 * 256 (spin-in-half, colour, site),
 // as four real 16x16x4 products per k-step.  One wave per chirality; the 4 k
-// values of a step are 4 consecutive sites with the same (spin, colour).
+// values of a step are 4 sites (stride 4) with the same (spin, colour).
 typedef float tf4 __attribute__((ext_vector_type(4)));
 typedef double td4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ tf4 tmfma(float a, float b, tf4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
@@ -255,20 +255,33 @@ __global__ __launch_bounds__(128) void k_restrict_mfma(Geom g, typename PT<C>::s
       part_re[t] = AT{0, 0, 0, 0};
       part_im[t] = AT{0, 0, 0, 0};
     }
-#pragma unroll 4
-    for (int l0 = 0; l0 < 256; l0 += 4) {
-      const int l = l0 + lk;
-      cpx<R> bv = ldcv<R>(vn, sidx(g, b, 6 * h + d, l));
-      if (!nok) bv = czero<R>();
+    // 16 sites per step: lane (ln, lk) loads sites l0 + 4 lk .. l0 + 4 lk + 3 of
+    // its P row and rhs with two wide loads; MFMA q takes site l0 + 4 lk + q in
+    // k-slot lk (the same site order in A and B, so the sum is unchanged)
+#pragma unroll 2
+    for (int l0 = 0; l0 < 256; l0 += 16) {
+      const int l = l0 + 4 * lk;
+      cpx<R> bv[4];
+      ld4c(vn + sidx(g, b, 6 * h + d, l), bv);
+      if (!nok)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bv[q] = czero<R>();
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         const int i = 16 * t + ln;
-        cpx<R> p = i < ntv ? ldcv<R>(P, pidx(g, ntv, b, h, i, d, l)) : czero<R>();
-        // A = conj(P): (p.re, -p.im)
-        part_re[t] = tmfma(p.re, bv.re, part_re[t]);
-        part_re[t] = tmfma(p.im, bv.im, part_re[t]);
-        part_im[t] = tmfma(p.re, bv.im, part_im[t]);
-        part_im[t] = tmfma(-p.im, bv.re, part_im[t]);
+        cpx<R> p[4];
+        if (i < ntv) ld4c(P + pidx(g, ntv, b, h, i, d, l), p);
+        else
+#pragma unroll
+          for (int q = 0; q < 4; ++q) p[q] = czero<R>();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          // A = conj(P): (p.re, -p.im)
+          part_re[t] = tmfma(p[q].re, bv[q].re, part_re[t]);
+          part_re[t] = tmfma(p[q].im, bv[q].im, part_re[t]);
+          part_im[t] = tmfma(p[q].re, bv[q].im, part_im[t]);
+          part_im[t] = tmfma(-p[q].im, bv[q].re, part_im[t]);
+        }
       }
     }
 #pragma unroll
