@@ -94,12 +94,26 @@ typedef struct {
   int l2_smooth;       /* levels = 3: GMRES smoothing steps on level 2 per level-2 cycle (2) */
 } qmg_params;
 
+#define QMG_STATS_HIST 32  /* entries of qmg_stats.relres_hist */
+
 typedef struct {
   int iters;           /* FGMRES iterations for this right-hand side */
   int restarts;        /* restart cycles */
   int coarse_iters;    /* total coarse GMRES iterations */
   double true_relres;  /* final ||b - (Q - tau) x|| / ||b||, FP64 */
   double seconds;      /* wall time of the whole batched solve */
+  /* time of the batched solve by phase, measured with HIP events on the solve's
+     stream (the same for every right-hand side of the batch): preconditioner
+     (V-cycles), FP64 operator products of the Arnoldi steps, Gram-Schmidt (dot
+     products, updates and their host round trips); initial residual, least
+     squares and restarts make up the rest of `seconds` */
+  double vcycle_seconds;
+  double apply_seconds;
+  double orth_seconds;
+  int n_hist;          /* entries used in relres_hist */
+  double relres_hist[QMG_STATS_HIST];  /* true relative residual in FP64 at the start of every
+                                          restart cycle this right-hand side took part in, the last
+                                          entry being the final one (first QMG_STATS_HIST kept) */
 } qmg_stats;
 
 qmg_params qmg_default_params(void);
@@ -301,13 +315,13 @@ typedef struct {
                           (Sec. 3.2, the method's choice for the eigenvalues of smallest
                           modulus); 1: Rayleigh-Ritz pairs V^H Q V s = theta s (the extraction
                           of the paper's Ritz versus harmonic Ritz comparison, Sec. 4) */
-  int both_signs;      /* 0: one target per step, the unlocked pair of smallest |theta|, and
-                          thick restarts keep the m_min of smallest |theta| (Alg. GD-lambdaAMG as
-                          printed); 1: each step targets the `block` unlocked pairs of smallest
+  int both_signs;      /* 1 (default): each step targets the `block` unlocked pairs of smallest
                           |theta| of each sign (2 block correction equations, one batched solve)
-                          and restarts keep both signs alternately.  Needs m_min + 2 block <= m_max.
-                          On fields whose lowest eigenvalues form well separated clusters of each
-                          sign, 0 can lock the smallest pairs of one sign only; 1 finds both */
+                          and thick restarts keep both signs alternately; needs
+                          m_min + 2 block <= m_max.  0: one target per step, the unlocked pair of
+                          smallest |theta|, restarts keep the m_min of smallest |theta|
+                          (Alg. GD-lambdaAMG as printed), which on a nearly symmetric spectrum can
+                          lock the smallest pairs of one sign only instead of the smallest |lambda| */
 } qmg_eig_params;
 
 typedef struct {

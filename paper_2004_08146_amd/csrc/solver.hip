@@ -439,6 +439,22 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
     if (!std::isfinite(bnorm[k])) return set_err(c, QMG_E_NUMERIC, "non-finite right-hand side");
   std::vector<int> iters(nrhs, 0), restarts(nrhs, 0), cits(nrhs, 0);
   std::vector<double> relres(nrhs, 0.0), rnorm(nrhs, 0.0);
+  std::vector<std::vector<double>> hist(nrhs);
+  std::vector<char> done(nrhs, 0);
+  // phase timing: four events per Arnoldi step (before the V-cycle, after it,
+  // after the product, after the Gram-Schmidt), read once the solve has synchronised
+  std::vector<hipEvent_t> evs;
+  struct EvPool {
+    std::vector<hipEvent_t>& v;
+    ~EvPool() { for (hipEvent_t e : v) (void)hipEventDestroy(e); }
+  } ev_pool{evs};
+  auto mark = [&]() -> hipError_t {
+    hipEvent_t ev;
+    hipError_t er = hipEventCreate(&ev);
+    if (er != hipSuccess) return er;
+    evs.push_back(ev);
+    return hipEventRecord(ev, s);
+  };
   // the working batch: na columns, column i is the caller's column cols[i]
   int na = nrhs;
   std::vector<int> cols(nrhs);
@@ -462,6 +478,8 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
       relres[k] = bnorm[k] > 0 ? beta[i] / bnorm[k] : 0.0;
       act[i] = relres[k] > prm->tol;
       nact += act[i];
+      if (!done[k]) hist[k].push_back(relres[k]);
+      if (!act[i]) done[k] = 1;
     }
     if (nact == 0 || total >= prm->maxiter) break;
     if (nact <= (3 * na) / 4) {
@@ -518,13 +536,19 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
     for (int jj = 0; jj < m; ++jj) {
       int ci = 0;
       void* w = sp.at(V, jj + 1);
+      e = mark();
+      if (e != hipSuccess) return hip_err(c, e, "event");
       st = solver_vcycle(c, zat(jj), sp.at(V, jj), tw.data(), na, prm, &ci, s, zprec);
       if (st != QMG_OK) return st;
-      e = launch_dslash_d_in(c, w, zat(jj), zprec, tw.data(), na, s, mode);
+      e = mark();
+      if (e == hipSuccess) e = launch_dslash_d_in(c, w, zat(jj), zprec, tw.data(), na, s, mode);
+      if (e == hipSuccess) e = mark();
       if (e != hipSuccess) return hip_err(c, e, "apply");
       std::vector<std::vector<cd>> h;
       st = sp.arnoldi(h, V, jj, w, &sig);
       if (st != QMG_OK) return st;
+      e = mark();
+      if (e != hipSuccess) return hip_err(c, e, "event");
       bool all = true;
       for (int i = 0; i < na; ++i) {
         if (!act[i]) { a[i] = 0.0; continue; }
@@ -573,6 +597,12 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_err(c, e, "sync");
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  double ph[3] = {0.0, 0.0, 0.0};
+  for (size_t i = 0; i + 3 < evs.size(); i += 4)
+    for (int q = 0; q < 3; ++q) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, evs[i + q], evs[i + q + 1]) == hipSuccess) ph[q] += 1e-3 * ms;
+    }
   bool conv = true;
   for (int k = 0; k < nrhs; ++k) {
     conv = conv && relres[k] <= prm->tol;
@@ -582,6 +612,12 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
       stats[k].coarse_iters = cits[k];
       stats[k].true_relres = relres[k];
       stats[k].seconds = secs;
+      stats[k].vcycle_seconds = ph[0];
+      stats[k].apply_seconds = ph[1];
+      stats[k].orth_seconds = ph[2];
+      const int nh = (int)std::min<size_t>(hist[k].size(), QMG_STATS_HIST);
+      stats[k].n_hist = nh;
+      for (int i = 0; i < QMG_STATS_HIST; ++i) stats[k].relres_hist[i] = i < nh ? hist[k][i] : 0.0;
     }
   }
   return conv ? QMG_OK : QMG_NOT_CONVERGED;

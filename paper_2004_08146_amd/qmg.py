@@ -39,12 +39,20 @@ class Params(ctypes.Structure):
                 ("levels", ctypes.c_int), ("l3_iters", ctypes.c_int), ("l2_smooth", ctypes.c_int)]
 
 
+STATS_HIST = 32
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("coarse_iters", ctypes.c_int),
-                ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("vcycle_seconds", ctypes.c_double), ("apply_seconds", ctypes.c_double),
+                ("orth_seconds", ctypes.c_double), ("n_hist", ctypes.c_int),
+                ("relres_hist", ctypes.c_double * STATS_HIST)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "relres_hist"}
+        d["relres_hist"] = list(self.relres_hist[:self.n_hist])
+        return d
 
 
 class EigParams(ctypes.Structure):

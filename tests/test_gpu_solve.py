@@ -169,3 +169,35 @@ def test_solve_batch_compaction_writes_back_every_column():
         x1 = lat.field(1)
         st1, s1 = lat.solve_shifted(x1, lat.pack(dev(b[k:k + 1])), [taus[k]], 1, prm)
         assert st1 == 0 and abs(s1[0]["iters"] - its[k]) <= 1, (k, s1[0]["iters"], its[k])
+
+
+def test_solve_statistics_history_and_phases():
+    """The per-rhs statistics of a batched solve: the true relative residual at the start of
+    every restart cycle (1 at x = 0, non-increasing up to rounding, the last entry the final
+    residual, one entry more than restart cycles), and the phase times (V-cycles, FP64
+    products, Gram-Schmidt) positive and within the wall time of the solve."""
+    case("solve statistics")
+    qmg = need_gpu()
+    dims = (8, 8, 8, 8)
+    U = random_links(dims, 0.5, seed_for(4, "U"))
+    lat = qmg.Lattice(dims, (4, 4, 4, 4))
+    lat.set_gauge(dev(U), -0.8, 1.0)
+    ntv = 12
+    W = lat.pack(dev(random_test_vectors(dims, ntv, seed_for(4, "W"))))
+    lat.setup_mg(W, ntv, setup_iters=3, smooth=3)
+    nrhs = 4
+    taus = [0.03 * (k - 1.5) for k in range(nrhs)]
+    b = random_spinors(dims, nrhs, seed_for(4, "b") + 11)
+    prm = qmg.default_params(mg_prec="f32", restart=3, maxiter=300)
+    x = lat.field(nrhs)
+    st, stats = lat.solve_shifted(x, lat.pack(dev(b)), taus, nrhs, prm)
+    assert st == 0
+    for s in stats:
+        h = s["relres_hist"]
+        print("restarts", s["restarts"], "history", ["%.2e" % v for v in h], flush=True)
+        assert s["n_hist"] == s["restarts"] + 1 == len(h)
+        assert abs(h[0] - 1.0) < 1e-12
+        assert h[-1] == s["true_relres"] <= 1e-10
+        assert all(h[i + 1] <= h[i] * (1 + 1e-6) for i in range(len(h) - 1))
+        ph = (s["vcycle_seconds"], s["apply_seconds"], s["orth_seconds"])
+        assert all(p > 0 for p in ph) and sum(ph) <= s["seconds"], (ph, s["seconds"])
