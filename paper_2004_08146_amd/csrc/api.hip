@@ -220,7 +220,7 @@ qmg_eig_params qmg_default_eig_params(void) {
   e.solve.mg_prec = QMG_F32;
   e.solve.restart = 5;
   e.extraction = 0;
-  e.both_signs = 0;
+  e.both_signs = 1;
   return e;
 }
 

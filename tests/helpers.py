@@ -1,4 +1,6 @@
 """Shared test utilities: oracle evaluation at sampled sites, error norms."""
+import os
+
 import numpy as np
 
 from oracle import clover as oclover
@@ -6,9 +8,13 @@ from oracle import dirac
 
 
 def rel_err(a, b):
+    """max |a - b| / max |b|; the value is also printed with the running test's
+    name (visible with pytest -s), so the measured errors can be tabulated."""
     a = np.asarray(a)
     b = np.asarray(b)
-    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+    v = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+    print("[rel_err] %s %.3e" % (os.environ.get("PYTEST_CURRENT_TEST", "").split(" ")[0], v), flush=True)
+    return v
 
 
 def window(dims, x, radius=2):

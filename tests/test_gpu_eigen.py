@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _run(dims, block, m0, ntv, nev, mmin, mmax, cfg, update=1, seed=4, nblk=1, l3=None, extraction=0,
-         maxiter=3000, both_signs=0):
+         maxiter=3000, both_signs=None):
     qmg = need_gpu()
     U = random_links(dims, 0.5, seed_for(cfg, "U"))
     lat = qmg.Lattice(dims, block)
@@ -29,8 +29,9 @@ def _run(dims, block, m0, ntv, nev, mmin, mmax, cfg, update=1, seed=4, nblk=1, l
         solve = {"levels": 3, "coarse_maxiter": 3, "l3_iters": 8, "l2_smooth": 2}
     t0 = lat.pack(dev(random_spinors(dims, 1, seed_for(cfg, "x") + seed)))
     X = lat.field(nev)
+    kw = {} if both_signs is None else {"both_signs": both_signs}  # None: the library's default (1)
     prm = qmg.default_eig_params(m_min=mmin, m_max=mmax, maxiter=maxiter, update_interp=update, block=nblk,
-                                 solve=solve, extraction=extraction, both_signs=both_signs)
+                                 solve=solve, extraction=extraction, **kw)
     st, lam, stats = lat.eigensolve(nev, X, t0, V0=W, n0=ntv, params=prm)
     return qmg, lat, U, st, lam, host(lat.unpack(X, nev)), stats
 
@@ -54,24 +55,27 @@ def _test_name():
 
 def _match(lam, ref, atol):
     """The locked eigenvalues, sorted, against the oracle's; prints the largest difference."""
+    if len(ref) == 0:
+        return len(lam) == 0
     d = np.abs(np.sort(lam) - np.sort(ref)).max()
     print("[eig_err] %s %.3e" % (_test_name(), d), flush=True)
     return d <= atol
 
 
-@pytest.mark.parametrize("nblk", [1, 4])
-def test_eigensolve_4x4_matches_dense_oracle(nblk):
+@pytest.mark.parametrize("nblk,both", [(1, 0), (4, 0), (1, 1), (4, 1)])
+def test_eigensolve_4x4_matches_dense_oracle(nblk, both):
     """4^4 lattice, 2^4 blocks, clover, 8 test vectors: the locked eigenvalues are
     the oracle's smallest-modulus ones, with restarts (m_max = 20) on the way;
-    one target per step and four targets solved as one multi-shift batch."""
-    case("eigensolve 4^4 vs dense oracle, block %d" % nblk)
+    one target per step and four targets solved as one multi-shift batch, with the
+    printed target rule and with targets of both signs (the default)."""
+    case("eigensolve 4^4 vs dense oracle, block %d, both signs %d" % (nblk, both))
     dims, m0 = (4, 4, 4, 4), -0.5
     U = random_links(dims, 0.5, seed_for(9, "U"))
     ref, _ = eigen.smallest_eigenpairs(U, m0, oclover.clover_term(U, 1.0), 40)
     # pick nev at a clear gap in |lambda| so "the nev smallest" is unambiguous
     gaps = np.diff(np.abs(ref))
     nev = 10 + int(np.argmax(gaps[9:20] > 1e-3))
-    qmg, lat, U2, st, lam, X, stats = _run(dims, (2, 2, 2, 2), m0, 8, nev, 10, 20, 9, nblk=nblk)
+    qmg, lat, U2, st, lam, X, stats = _run(dims, (2, 2, 2, 2), m0, 8, nev, 10, 20, 9, nblk=nblk, both_signs=both)
     assert st == 0 and stats["converged"] == nev, stats
     assert _match(lam, ref[:nev], 1e-9)
     _check_pairs(U, m0, lam, X, 1.1e-8)
@@ -85,7 +89,9 @@ def test_eigensolve_8x4_pairs_valid(nblk):
     <= 1e-8 under the oracle's operator and the vectors are orthonormal."""
     case("eigensolve 8^4 pairs, block %d" % nblk)
     dims, m0 = (8, 8, 8, 8), -0.5
-    qmg, lat, U, st, lam, X, stats = _run(dims, (4, 4, 4, 4), m0, 4, 8, 10, 20, 10, nblk=nblk)
+    # 2 x 8 targets of both signs would not fit m_max = 20: block 8 takes the printed rule
+    qmg, lat, U, st, lam, X, stats = _run(dims, (4, 4, 4, 4), m0, 4, 8, 10, 20, 10, nblk=nblk,
+                                          both_signs=0 if nblk > 4 else None)
     assert st == 0 and stats["converged"] == 8, stats
     _check_pairs(U, m0, lam, X, 1.1e-8)
     assert stats["interp_updates"] >= 1
@@ -133,7 +139,7 @@ def test_eigensolve_8x4_printed_rule_and_rayleigh_ritz():
     ref = np.array(g["lambda"])
     dims, m0 = tuple(g["dims"]), g["m0"]
     qmg, lat, U, st, lam, X, stats = _run(dims, (4, 4, 4, 4), m0, 12, 50, 30, 50, g["seed_config"],
-                                          maxiter=6000)
+                                          maxiter=6000, both_signs=0)
     print("printed rule: %d pairs (%d negative) in %d outer iterations" % (
         stats["converged"], int(np.sum(lam < 0)), stats["iters"]), flush=True)
     assert st == 0 and stats["converged"] == 50
@@ -145,7 +151,7 @@ def test_eigensolve_8x4_printed_rule_and_rayleigh_ritz():
         assert _match(mine[:n], theirs[:n], 1e-8), sign
     budget = stats["iters"]
     qmg, lat, U, st_r, lam_r, X_r, stats_r = _run(dims, (4, 4, 4, 4), m0, 12, 50, 30, 50, g["seed_config"],
-                                                  extraction=1, maxiter=budget)
+                                                  extraction=1, maxiter=budget, both_signs=0)
     print("Rayleigh-Ritz: %d pairs in %d outer iterations" % (stats_r["converged"], stats_r["iters"]), flush=True)
     assert stats_r["converged"] < stats["converged"]
     if stats_r["converged"]:
