@@ -88,6 +88,7 @@ bool load_cache(qmg_ctx* c, const std::string& path, const std::string& key) {
 
 qmg_status tune_run(qmg_ctx* c, const char* path) {
   const std::string key = tune_key(c);
+  drop_graphs(c);  // recorded V-cycles hold the previous kernel choices
   if (path && load_cache(c, path, key)) {
     c->tune.tuned = true;
     return QMG_OK;
