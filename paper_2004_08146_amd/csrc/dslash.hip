@@ -27,6 +27,7 @@ struct DsArgs {
   int remap;
   const int* tord;  // block ids in work order: tiles of tb blocks, each tile's rhs groups back to back
   int tb;
+  int nt_out;       // 1: the output is written with non-temporal stores (streamed past the caches)
   Geom g;
   double tau[QMG_MAXRHS];
 };
@@ -238,7 +239,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W > 0 ? W :
         cpx<C> v = o.s[s][c] - C(0.5) * acc[r].s[s][c];
         if (MODE == 0) v = (s < 2) ? v - tau * self.s[s][c] : v + tau * self.s[s][c];
         else v = (s < 2) ? v - tau * self.s[s][c] : -v - tau * self.s[s][c];
-        sto(out, ((b * 12u + (uint32_t)(3 * s + c)) << 8) + l, vc(v, (P*)nullptr));
+        const uint32_t o = ((b * 12u + (uint32_t)(3 * s + c)) << 8) + l;
+        if (a.nt_out) sto_nt(out, o, vc(v, (P*)nullptr));
+        else sto(out, o, vc(v, (P*)nullptr));
       }
   }
   }
@@ -265,6 +268,7 @@ void launch_t(const qmg_ctx* c, void* out, const void* in, const double* tau, in
   a.remap = c->tune.dslash_xcd_remap;
   a.tord = c->d_tord;
   a.tb = c->tile_blocks;
+  a.nt_out = 0;
   a.g = c->g;
   for (int i = 0; i < QMG_MAXRHS; ++i) a.tau[i] = i < nrhs ? tau[i] : 0.0;
   const bool b44 = c->g.block[0] == 4 && c->g.block[1] == 4 && c->g.block[2] == 4 && c->g.block[3] == 4;
@@ -280,7 +284,15 @@ void launch_t(const qmg_ctx* c, void* out, const void* in, const double* tau, in
       case 7: launch44<S, CLOVER, MODE, 4, 0>(a, c->g.nb, s); break;
       case 8: launch44<S, CLOVER, MODE, 1, 2, true>(a, c->g.nb, s); break;
       case 9: launch44<S, CLOVER, MODE, 2, 0, true>(a, c->g.nb, s); break;
-      default: launch44<S, CLOVER, MODE, 2, 2, true>(a, c->g.nb, s); break;
+      case 10: launch44<S, CLOVER, MODE, 2, 2, true>(a, c->g.nb, s); break;
+      default: {
+        // variant 1 with the output streamed past the caches, which then keep the
+        // neighbour spinors, links and clover for longer
+        DsArgs<S, SI> an = a;
+        an.nt_out = 1;
+        launch44<S, CLOVER, MODE, 1, 0>(an, c->g.nb, s);
+        break;
+      }
     }
     return;
   }

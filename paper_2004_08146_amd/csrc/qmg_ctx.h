@@ -21,9 +21,10 @@ inline int coarse_prec(int p) { return p == QMG_F64 ? QMG_F64 : QMG_F32; }
 // generic kernel (any block shape).
 struct DsVariant { int R, W; };
 // variants 8..10 walk all rhs groups of a block inside one work-group
+// variant 11 is variant 1 writing its output with non-temporal stores
 constexpr DsVariant kDsVariants[] = {{0, 0}, {1, 0}, {1, 2}, {1, 3}, {1, 4}, {2, 0}, {2, 2}, {4, 0},
-                                     {1, 2}, {2, 0}, {2, 2}};
-constexpr int kNumDsVariants = 11;
+                                     {1, 2}, {2, 0}, {2, 2}, {1, 0}};
+constexpr int kNumDsVariants = 12;
 // tiles of blocks (extent per direction, clamped to a divisor of the block grid)
 constexpr int kTileShapes[][4] = {{1, 1, 1, 1}, {2, 2, 2, 2}, {2, 2, 2, 4}, {2, 2, 4, 4},
                                   {1, 2, 4, 8}, {2, 2, 4, 8}, {1, 1, 2, 8}, {1, 2, 2, 4}};

@@ -95,6 +95,21 @@ template <typename P> QMG_HD P ldo(const P* base, uint32_t elem) {
 template <typename P> QMG_HD void sto(P* base, uint32_t elem, P v) {
   *reinterpret_cast<P*>(reinterpret_cast<char*>(base) + (size_t)(elem * (uint32_t)sizeof(P))) = v;
 }
+// store through the non-temporal path (the line is not kept in the caches)
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+QMG_HD void sto_nt(double2* base, uint32_t elem, double2 v) {
+  __builtin_nontemporal_store(nt_d2{v.x, v.y}, reinterpret_cast<nt_d2*>(reinterpret_cast<char*>(base) +
+                                                                       (size_t)(elem * (uint32_t)sizeof(double2))));
+}
+QMG_HD void sto_nt(float2* base, uint32_t elem, float2 v) {
+  __builtin_nontemporal_store(nt_f2{v.x, v.y}, reinterpret_cast<nt_f2*>(reinterpret_cast<char*>(base) +
+                                                                      (size_t)(elem * (uint32_t)sizeof(float2))));
+}
+QMG_HD void sto_nt(uint32_t* base, uint32_t elem, uint32_t v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) +
+                                                            (size_t)(elem * (uint32_t)sizeof(uint32_t))));
+}
 QMG_HD cpx<double> cv(double2 v) { return {v.x, v.y}; }
 QMG_HD cpx<float> cv(float2 v) { return {v.x, v.y}; }
 QMG_HD cpx<float> cv(uint32_t v) { return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)}; }

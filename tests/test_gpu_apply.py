@@ -153,7 +153,7 @@ def test_stencil_tile_orders(order, variant, tmp_path):
         assert rel_err(out[k], dirac.apply_Q_shifted(U, pin[k], -0.8, taus[k], C)) < 1e-13
 
 
-@pytest.mark.parametrize("variant", range(11))
+@pytest.mark.parametrize("variant", range(12))
 def test_stencil_variants(variant, tmp_path):
     """Every launch variant of the stencil (generic, 4^4 kernels with 1/2/4 rhs per
     thread and occupancy targets) against the oracle, with a ragged rhs batch."""
