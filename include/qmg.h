@@ -92,6 +92,10 @@ typedef struct {
                           fixed steps) */
   int l3_iters;        /* levels = 3: GMRES steps on the level-3 operator per level-2 cycle (8) */
   int l2_smooth;       /* levels = 3: GMRES smoothing steps on level 2 per level-2 cycle (2) */
+  int x0;              /* 0 (default): the solve starts from x = 0; 1: the x passed in is the
+                          initial guess (FP64 finite values; a solve that stopped at maxiter resumes
+                          from its own result, since each restart cycle starts from the true
+                          residual of the current x) */
 } qmg_params;
 
 #define QMG_STATS_HIST 32  /* entries of qmg_stats.relres_hist */

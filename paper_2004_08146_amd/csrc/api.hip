@@ -203,6 +203,7 @@ qmg_params qmg_default_params(void) {
   p.levels = 2;
   p.l3_iters = 8;
   p.l2_smooth = 2;
+  p.x0 = 0;
   return p;
 }
 
@@ -674,7 +675,8 @@ qmg_status qmg_solve_shifted(qmg_ctx* c, void* x, const void* b, const double* t
   qmg_params prm0 = prm ? *prm : qmg_default_params();
   QMG_TRY(check_prec(c, prm0.mg_prec));
   if (!(prm0.tol > 0) || prm0.maxiter < 1 || prm0.restart < 1 || prm0.nu_post < 0 || prm0.n_mr < 0 ||
-      prm0.coarse_maxiter < 1 || prm0.q_form < 0 || prm0.q_form > 1 || prm0.smoother < 0 || prm0.smoother > 1)
+      prm0.coarse_maxiter < 1 || prm0.q_form < 0 || prm0.q_form > 1 || prm0.smoother < 0 || prm0.smoother > 1 ||
+      prm0.x0 < 0 || prm0.x0 > 1)
     return set_err(c, QMG_E_ARG, "solve_shifted: bad parameters");
   QMG_TRY(check_levels(c, prm0));
   if (prm0.use_coarse) QMG_TRY(need_mg(c));

@@ -402,6 +402,7 @@ qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const
   ip.tol = prm->inner_tol;
   ip.maxiter = prm->inner_maxiter;
   ip.use_graph = 0;  // every correction equation has its own shift
+  ip.x0 = 0;         // correction equations start from t = 0
   int iters = 0, inner = 0, updates = 0;
   bool done = false;
   std::vector<qmg_stats> ist(ntgt);

@@ -426,8 +426,14 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
   const int mode = prm->q_form ? 1 : 0;
   hipError_t e = prm->q_form ? hipMemcpyAsync(f, b, bb, hipMemcpyDeviceToDevice, s)
                              : launch_gamma5_bs(QMG_F64, f, b, n * nrhs, c->g.bs_log, s);
-  if (e == hipSuccess) e = launch_fill_zero(x, bb, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(r, f, bb, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && !prm->x0) e = launch_fill_zero(x, bb, s);
+  if (prm->x0) {
+    // initial guess from the caller: r = Gamma5 b - A_tau x (or b - (Q - tau) x)
+    if (e == hipSuccess) e = launch_dslash(c, QMG_F64, r, x, tau, nrhs, mode, s);
+    if (e == hipSuccess) e = launch_xmy(QMG_F64, r, f, n, n, nrhs, s);
+  } else if (e == hipSuccess) {
+    e = hipMemcpyAsync(r, f, bb, hipMemcpyDeviceToDevice, s);
+  }
   if (e != hipSuccess) return hip_err(c, e, "fgmres init");
   std::vector<double> bnorm;
   {

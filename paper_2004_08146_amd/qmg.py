@@ -36,7 +36,8 @@ class Params(ctypes.Structure):
                 ("nu_post", ctypes.c_int), ("n_mr", ctypes.c_int), ("coarse_maxiter", ctypes.c_int),
                 ("coarse_tol", ctypes.c_double), ("mg_prec", ctypes.c_int), ("use_coarse", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("q_form", ctypes.c_int), ("smoother", ctypes.c_int),
-                ("levels", ctypes.c_int), ("l3_iters", ctypes.c_int), ("l2_smooth", ctypes.c_int)]
+                ("levels", ctypes.c_int), ("l3_iters", ctypes.c_int), ("l2_smooth", ctypes.c_int),
+                ("x0", ctypes.c_int)]
 
 
 STATS_HIST = 32

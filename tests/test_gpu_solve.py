@@ -201,3 +201,39 @@ def test_solve_statistics_history_and_phases():
         assert all(h[i + 1] <= h[i] * (1 + 1e-6) for i in range(len(h) - 1))
         ph = (s["vcycle_seconds"], s["apply_seconds"], s["orth_seconds"])
         assert all(p > 0 for p in ph) and sum(ph) <= s["seconds"], (ph, s["seconds"])
+
+
+def test_solve_resumes_from_initial_guess():
+    """qmg_params.x0 = 1: a solve cut off by maxiter resumes from its own x (its first
+    residual is the one the stopped solve ended with) and converges in about the
+    iterations a single solve takes; a converged x passed back needs no iteration."""
+    case("solve resume from x0")
+    qmg = need_gpu()
+    dims, m0, csw = (8, 8, 8, 8), -0.8, 1.0
+    U = random_links(dims, 0.5, seed_for(4, "U"))
+    lat = qmg.Lattice(dims, (4, 4, 4, 4))
+    lat.set_gauge(dev(U), m0, csw)
+    ntv = 12
+    W = lat.pack(dev(random_test_vectors(dims, ntv, seed_for(4, "W"))))
+    lat.setup_mg(W, ntv, setup_iters=3, smooth=3)
+    nrhs, taus = 2, [0.01, -0.02]
+    b = random_spinors(dims, nrhs, seed_for(4, "b") + 13)
+    bg = lat.pack(dev(b))
+    x1 = lat.field(nrhs)
+    st1, s1 = lat.solve_shifted(x1, bg, taus, nrhs, qmg.default_params(mg_prec="f32", restart=4, maxiter=300))
+    assert st1 == 0
+    x = lat.field(nrhs)
+    st_a, sa = lat.solve_shifted(x, bg, taus, nrhs, qmg.default_params(mg_prec="f32", restart=4, maxiter=5))
+    assert st_a == 1 and all(s["true_relres"] > 1e-10 for s in sa)
+    st_b, sb = lat.solve_shifted(x, bg, taus, nrhs, qmg.default_params(mg_prec="f32", restart=4, maxiter=300, x0=1))
+    assert st_b == 0
+    for k in range(nrhs):
+        print("single", s1[k]["iters"], "resumed", sa[k]["iters"], "+", sb[k]["iters"], flush=True)
+        assert abs(sb[k]["relres_hist"][0] - sa[k]["true_relres"]) <= 1e-12 * sa[k]["true_relres"]
+        assert abs(sa[k]["iters"] + sb[k]["iters"] - s1[k]["iters"]) <= 4
+    xs = host(lat.unpack(x, nrhs))
+    C = oclover.clover_term(U, csw)
+    for k in range(nrhs):
+        assert _true_relres_oracle(U, m0, C, xs[k], b[k], taus[k]) <= 1.5e-10
+    st_c, sc = lat.solve_shifted(x, bg, taus, nrhs, qmg.default_params(mg_prec="f32", restart=4, x0=1))
+    assert st_c == 0 and all(s["iters"] == 0 and s["true_relres"] <= 1e-10 for s in sc)
