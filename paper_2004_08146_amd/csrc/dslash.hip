@@ -272,11 +272,7 @@ void launch_t(const qmg_ctx* c, void* out, const void* in, const double* tau, in
   a.g = c->g;
   for (int i = 0; i < QMG_MAXRHS; ++i) a.tau[i] = i < nrhs ? tau[i] : 0.0;
   const bool b44 = c->g.block[0] == 4 && c->g.block[1] == 4 && c->g.block[2] == 4 && c->g.block[3] == 4;
-  int var = c->tune.force_variant >= 0 ? c->tune.force_variant : c->tune.dslash[p][nrhs == 1 ? 0 : 1];
-  // the tuner times FP64 products on FP64 input; on FP32- or BF16-stored input (the
-  // FGMRES product on the preconditioned directions, read next by the Gram-Schmidt)
-  // the non-temporal output measured slower (64x32^3, 16 rhs: 5.46 against 5.17 ms)
-  if (!std::is_same<S, SI>::value && c->tune.force_variant < 0 && var == 11) var = 1;
+  const int var = c->tune.force_variant >= 0 ? c->tune.force_variant : c->tune.dslash[p][nrhs == 1 ? 0 : 1];
   if (b44 && var > 0 && var < kNumDsVariants) {
     switch (var) {
       case 1: launch44<S, CLOVER, MODE, 1, 0>(a, c->g.nb, s); break;

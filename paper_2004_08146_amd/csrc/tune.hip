@@ -162,7 +162,7 @@ qmg_status tune_run(qmg_ctx* c, const char* path) {
     js << ",\n  \"" << key << "|xcd_remap\": " << rm;
   }
   // work order of the stencil (tiles of blocks) under the chosen mapping and
-  // variants: the sum over FP64 / FP32 with 1 and 16 rhs decides
+  // variants: the sum over FP64 / FP32 with 1 and 16 rhs and the FGMRES product decides
   if (st == QMG_OK && b44) {
     const size_t bytes = field_elems(c) * cbytes(QMG_F64) * 16;
     void* in = ws_get(c, "tune_in", bytes);
@@ -175,12 +175,19 @@ qmg_status tune_run(qmg_ctx* c, const char* path) {
     for (int o = 0; o < kNumDsOrders && st == QMG_OK; ++o) {
       st = set_ds_order(c, o);
       double tot = 0.0;
-      for (int p = 0; p < 2 && st == QMG_OK; ++p)
+      // FP64 and FP32 with 1 and 16 rhs, and the FGMRES product (FP64 output from
+      // 16 FP32-stored directions, D - tau Gamma5), the most frequent FP64 stencil use
+      for (int p = 0; p < 3 && st == QMG_OK; ++p)
         for (int cls = 0; cls < 2 && st == QMG_OK; ++cls) {
+          if (p == 2 && cls == 0) continue;
           const int n = cls == 0 ? 1 : 16;
-          hipError_t e = launch_dslash(c, p, out, in, tau.data(), n, 1, s);
+          auto go = [&]() {
+            return p == 2 ? launch_dslash_d_in(c, out, in, QMG_F32, tau.data(), n, s, 0)
+                          : launch_dslash(c, p, out, in, tau.data(), n, 1, s);
+          };
+          hipError_t e = go();
           if (e == hipSuccess) e = hipEventRecord(e0, s);
-          for (int r = 0; r < 5 && e == hipSuccess; ++r) e = launch_dslash(c, p, out, in, tau.data(), n, 1, s);
+          for (int r = 0; r < 5 && e == hipSuccess; ++r) e = go();
           if (e == hipSuccess) e = hipEventRecord(e1, s);
           if (e == hipSuccess) e = hipEventSynchronize(e1);
           float ms = 0.f;
