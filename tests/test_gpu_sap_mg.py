@@ -34,7 +34,7 @@ def test_sap_parity(dims, block):
     got = host(lat.unpack(xg, nrhs))
     for k in range(nrhs):
         ref = sap.sap(op, f[k], x0[k], taus[k], block, 2, 3)
-        assert rel_err(got[k], ref) < 1e-12
+        assert rel_err(got[k], ref) < 1e-13
 
 
 def _force_sap(lat, tmp_path, dims, block, clover, v):
@@ -50,7 +50,7 @@ _SAP_REF = {}
 
 
 @pytest.mark.parametrize("sapv,nrhs", [(0, 2), (1, 2), (1, 5), (1, 16), (2, 2), (2, 5), (2, 16)])
-@pytest.mark.parametrize("prec,tol", [("f32", 2e-5), ("bf16", 5e-2)])
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-6), ("bf16", 5e-2)])
 def test_sap_reduced_precision(prec, tol, sapv, nrhs, tmp_path):
     """FP32 / BF16-storage SAP, all three kernels (generic; LDS-staged 4^4 with one or two
     rhs per work-group), on 2, 5 and 16 rhs with distinct shifts: 16 rhs is the solve's batch
@@ -76,15 +76,16 @@ def test_sap_reduced_precision(prec, tol, sapv, nrhs, tmp_path):
     assert max(errs) < tol, errs
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 2e-3)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-6)])
 def test_setup_parity(prec, tol):
     """qmg_setup_mg against the oracle's setup (smoothing on A_0 w = 0, then V-cycle inverse
     iterations with interpolation rebuilds): 8^4, 8 test vectors, 4 setup iterations, 3
     smoothing steps, coarse GMRES to 0.5 (at most 20 steps).  Both sides start from the same W.
     FP64 V-cycles: the iteration is nonlinear (minimal-residual steps, a coarse GMRES whose
-    length depends on a tolerance test) and repeated four times, so rounding-order differences
-    grow from 1e-15 to about 1e-12; 1e-9 bounds them.  FP32 V-cycles: each round adds FP32
-    rounding of the smoother output (~1e-6 relative) that the next rounds carry along."""
+    length depends on a tolerance test) and repeated four times; the rounding-order
+    differences measure about 1e-15, held to the FP64 bar of 1e-13.  FP32 V-cycles: each
+    round adds FP32 rounding of the smoother output; the result is renormalised, and the
+    difference measures about 3e-7, held to the FP32 bar of 1e-6."""
     case("setup parity 8^4 " + prec)
     dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
     qmg, lat, op = _op(dims, block)
@@ -142,7 +143,7 @@ def test_coarse_gmres_fixed_iterations():
     for k in range(2):
         ref, its, _ = krylov.gmres(lambda v: h.coarse.apply(v, taus[k]), r[k], 12)
         assert its == 12
-        assert rel_err(y[k], ref) < 1e-11
+        assert rel_err(y[k], ref) < 1e-13
 
 
 def test_vcycle_parity():
@@ -154,7 +155,7 @@ def test_vcycle_parity():
     prm = qmg.default_params(coarse_maxiter=10, coarse_tol=0.0, nu_post=2, n_mr=3)
     z = host(lat.unpack(lat.vcycle(lat.field(1), lat.pack(dev(r)), [0.02], 1, prm)))
     ref = h.vcycle(r[0], 0.02, 2, 3, 10, None)
-    assert rel_err(z[0], ref) < 1e-11
+    assert rel_err(z[0], ref) < 1e-13
 
 
 def test_rank_deficient_test_vectors_rejected():
@@ -167,7 +168,7 @@ def test_rank_deficient_test_vectors_rejected():
     assert e.value.status == -5
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-11), ("f32", 2e-5)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-6)])
 def test_vcycle_graph_replays(prec, tol):
     """The HIP-graph V-cycle (device-resident coarse GMRES, fixed steps): every replay,
     with eager work and synchronisations in between, matches the oracle V-cycle."""
@@ -267,7 +268,7 @@ def test_full_size_sap_and_restrict_sampled():
         ref = sap.sap(dirac.Operator(Uw, m0, C), fw, np.zeros_like(fw), tau, block, 1, 3)[inner]
         sl = tuple(slice(X[mu] * block[mu], (X[mu] + 1) * block[mu]) for mu in range(4))
         got = host(xs[0][sl])
-        assert rel_err(got, ref) < 1e-12
+        assert rel_err(got, ref) < 1e-13
         done += 1
     # restriction: the aggregate of block b only sees P_b (built from W on block b) and v on block b
     ntv = 24
