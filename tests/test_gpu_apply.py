@@ -102,8 +102,9 @@ def test_apply_Q_hermitian_and_dot():
 
 
 @pytest.mark.parametrize("prec,nrhs,tol", [("f64", 1, 1e-13), ("f32", 16, 1e-6)])
-def test_apply_full_size_sampled(prec, nrhs, tol):
-    """64x32^3, c_sw = 1, the bench configuration: sampled sites against the oracle."""
+def test_apply_full_size_sampled(prec, nrhs, tol, tmp_path):
+    """64x32^3, c_sw = 1, the bench configuration and the launch configuration the
+    autotuner picks there (as in the bench): sampled sites against the oracle."""
     case("apply 64x32^3 sampled %s nrhs=%d" % (prec, nrhs))
     qmg = need_gpu()
     dims = (64, 32, 32, 32)
@@ -111,6 +112,11 @@ def test_apply_full_size_sampled(prec, nrhs, tol):
     m0 = -0.8
     lat = qmg.Lattice(dims, (4, 4, 4, 4))
     lat.set_gauge(dev(U), m0, 1.0)
+    path = tmp_path / "tune.json"
+    lat.autotune(str(path))
+    cls = "|dslash|%s|%d\":" % (prec, 0 if nrhs == 1 else 1)
+    print("tuned:", [ln.strip() for ln in path.read_text().splitlines() if cls in ln or "ds_order\":" in ln],
+          flush=True)
     taus = [0.0025 * (2 * k - 15) for k in range(nrhs)]
     fin = lat.pack(dev(psi), prec)
     out = lat.unpack(lat.apply_Q_shifted(lat.field(nrhs, prec), fin, taus, nrhs, prec), nrhs, prec)
