@@ -241,6 +241,50 @@ def _block_window(U, f, X, block, csw, nwin=4):
     return U[sl], C, f[sl], tuple(inner)
 
 
+def test_full_size_sap_fp32_16rhs_tuned(tmp_path):
+    """64x32^3, c_sw = 1, the bench's SAP launch configuration: FP32, 16 right-hand sides with
+    their own shifts tau_k = 0.002 (2k - 15), the kernel the autotuner picks.  One sweep from
+    x = 0; for a colour-1 block the result depends only on f in the block and its 8
+    colour-0 neighbours, so the oracle's SAP on a 4^4-block window (FP64 links and clover, f
+    as the GPU stored it) reproduces it up to the FP32 arithmetic.  rhs 0 and 15, two sampled
+    blocks each."""
+    from gpu_common import big_inputs, torch
+    from synth import device_gaussian_spinors
+    case("full-size SAP FP32 16 rhs, tuned")
+    qmg = need_gpu()
+    dims, block = (64, 32, 32, 32), (4, 4, 4, 4)
+    U, _ = big_inputs(dims, 0.5, 5, 1)
+    m0, csw = -0.95, 1.0
+    lat = qmg.Lattice(dims, block)
+    lat.set_gauge(dev(U), m0, csw)
+    lat.autotune(str(tmp_path / "tune.json"))
+    nrhs = 16
+    taus = [0.002 * (2 * k - 15) for k in range(nrhs)]
+    fg = lat.pack(device_gaussian_spinors(dims, nrhs, seed_for(5, "b")), "f32")
+    xg = lat.field(nrhs, "f32")
+    lat.sap_smooth(xg, fg, taus, nrhs, nsweep=1, n_mr=3, prec="f32")
+    xs = lat.unpack(xg, nrhs, "f32")
+    fs = lat.unpack(fg, nrhs, "f32")
+    rng = np.random.default_rng(21)
+    nbk = [d // b for d, b in zip(dims, block)]
+    errs = []
+    for k in (0, nrhs - 1):
+        fk = host(fs[k])
+        done = 0
+        while done < 2:
+            X = [int(rng.integers(0, n)) for n in nbk]
+            if sum(X) % 2 != 1:
+                continue
+            Uw, C, fw, inner = _block_window(U, fk, X, block, csw)
+            ref = sap.sap(dirac.Operator(Uw, m0, C), fw, np.zeros_like(fw), taus[k], block, 1, 3)[inner]
+            sl = tuple(slice(X[mu] * block[mu], (X[mu] + 1) * block[mu]) for mu in range(4))
+            errs.append(rel_err(host(xs[k][sl]), ref))
+            done += 1
+        del fk
+    print("max rel err %.2e" % max(errs), flush=True)
+    assert max(errs) < 1e-6, errs
+
+
 def test_full_size_sap_and_restrict_sampled():
     """64x32^3, c_sw = 1, 16 rhs batch layout of the bench: one FP64 SAP sweep from x = 0 and the
     restriction, checked on sampled blocks.  For a colour-1 block the sweep depends only on f in the
