@@ -285,6 +285,66 @@ def test_full_size_sap_fp32_16rhs_tuned(tmp_path):
     assert max(errs) < 1e-6, errs
 
 
+def test_full_size_coarse_apply_fp32_16rhs_tuned(tmp_path):
+    """64x32^3, c_sw = 1, 24 test vectors: the coarse apply (D_c - tau_k Gamma5^c) in the bench's
+    launch configuration (FP32, 16 right-hand sides, the kernel the autotuner picks) on sampled
+    coarse sites.  Reference: D_c = P^H D P, so at coarse site X it needs P y on block X and its
+    8 neighbours only; the oracle prolongs there (P of each block from its own test vectors),
+    applies D on a 3-block window around X (links and clover of the big lattice) and restricts
+    on X.  The input is the FP32 vector the GPU read."""
+    from gpu_common import big_inputs
+    case("full-size coarse apply FP32 16 rhs, tuned")
+    qmg = need_gpu()
+    dims, block = (64, 32, 32, 32), (4, 4, 4, 4)
+    U, _ = big_inputs(dims, 0.5, 5, 1)
+    m0, csw, ntv = -0.95, 1.0, 24
+    lat = qmg.Lattice(dims, block)
+    lat.set_gauge(dev(U), m0, csw)
+    W = random_test_vectors(dims, ntv, seed_for(5, "W"))
+    lat.set_test_vectors(lat.pack(dev(W)), ntv)
+    lat.autotune(str(tmp_path / "tune.json"))
+    order = lat.coarse_site_order()
+    nrhs = 16
+    taus = [0.002 * (2 * k - 15) for k in range(nrhs)]
+    rng = np.random.default_rng(8)
+    ylex = (rng.standard_normal((nrhs, len(order), 2 * ntv))
+            + 1j * rng.standard_normal((nrhs, len(order), 2 * ntv))).astype(np.complex64)
+    yg = dev(lex_to_coarse(ylex, order).view(np.float32))
+    out = coarse_to_lex(host(lat.apply_coarse(lat.coarse(nrhs, "f32"), yg, taus, nrhs, "f32")).view(np.complex64),
+                        order, ntv)
+    nbk = [d // b for d, b in zip(dims, block)]
+
+    def lex(Y):
+        return ((Y[0] * nbk[1] + Y[1]) * nbk[2] + Y[2]) * nbk[3] + Y[3]
+
+    def gslice(Y):
+        return tuple(slice(Y[mu] * block[mu], (Y[mu] + 1) * block[mu]) for mu in range(4))
+
+    errs = []
+    for _ in range(3):
+        X = [int(rng.integers(0, n)) for n in nbk]
+        idx = [((X[mu] - 1) * block[mu] + np.arange(3 * block[mu])) % dims[mu] for mu in range(4)]
+        Uw = U[np.ix_(*idx)]
+        Cw = oclover.clover_term(Uw, csw)
+        nine = [(1, 1, 1, 1)] + [tuple(1 + (s if m == mu else 0) for m in range(4))
+                                 for mu in range(4) for s in (1, -1)]
+        Ps = {}
+        for wpos in nine:
+            Yg = [(X[mu] + wpos[mu] - 1) % nbk[mu] for mu in range(4)]
+            Ps[wpos] = (mg.build_P([w[gslice(Yg)] for w in W], block), lex(Yg))
+        PX, lX = Ps[(1, 1, 1, 1)]
+        for k in (0, nrhs - 1):
+            v = np.zeros(tuple(3 * b for b in block) + (4, 3), dtype=np.complex128)
+            for wpos, (P, ly) in Ps.items():
+                v[gslice(wpos)] = mg.prolong(P, ylex[k][ly][None, :].astype(np.complex128), block, block)
+            Dv = dirac.apply_D(Uw, v, m0, Cw)[gslice((1, 1, 1, 1))]
+            yX = ylex[k][lX].astype(np.complex128)
+            ref = mg.restrict(PX, Dv, block)[0] - taus[k] * mg.gamma5_coarse(yX)
+            errs.append(rel_err(out[k][lX], ref))
+    print("max rel err %.2e" % max(errs), flush=True)
+    assert max(errs) < 1e-5, errs
+
+
 def test_full_size_sap_and_restrict_sampled():
     """64x32^3, c_sw = 1, 16 rhs batch layout of the bench: one FP64 SAP sweep from x = 0 and the
     restriction, checked on sampled blocks.  For a colour-1 block the sweep depends only on f in the
