@@ -286,9 +286,9 @@ def test_full_size_sap_fp32_16rhs_tuned(tmp_path):
 
 
 def test_full_size_coarse_apply_fp32_16rhs_tuned(tmp_path):
-    """64x32^3, c_sw = 1, 24 test vectors: the coarse apply (D_c - tau_k Gamma5^c) in the bench's
-    launch configuration (FP32, 16 right-hand sides, the kernel the autotuner picks) on sampled
-    coarse sites.  Reference: D_c = P^H D P, so at coarse site X it needs P y on block X and its
+    """64x32^3, c_sw = 1, 24 test vectors: the coarse apply (D_c - tau_k Gamma5^c), the restriction
+    and the prolongation in the bench's launch configuration (FP32, 16 right-hand sides, the
+    kernels the autotuner picks) on sampled coarse sites and blocks.  Reference: D_c = P^H D P, so at coarse site X it needs P y on block X and its
     8 neighbours only; the oracle prolongs there (P of each block from its own test vectors),
     applies D on a 3-block window around X (links and clover of the big lattice) and restricts
     on X.  The input is the FP32 vector the GPU read."""
@@ -343,6 +343,23 @@ def test_full_size_coarse_apply_fp32_16rhs_tuned(tmp_path):
             errs.append(rel_err(out[k][lX], ref))
     print("max rel err %.2e" % max(errs), flush=True)
     assert max(errs) < 1e-5, errs
+    # restriction and prolongation of 16 FP32 fields (the MFMA kernels), sampled blocks: the
+    # aggregate of block b only sees P_b and the field on block b
+    from synth import device_gaussian_spinors
+    vg = lat.pack(device_gaussian_spinors(dims, nrhs, seed_for(5, "x")), "f32")
+    vs = lat.unpack(vg, nrhs, "f32")
+    yr = coarse_to_lex(host(lat.restrict(lat.coarse(nrhs, "f32"), vg, nrhs, "f32")).view(np.complex64), order, ntv)
+    pv = lat.unpack(lat.prolong(lat.field(nrhs, "f32"), yg, nrhs, "f32"), nrhs, "f32")
+    terr, perr = [], []
+    for _ in range(3):
+        Y = [int(rng.integers(0, n)) for n in nbk]
+        P = mg.build_P([w[gslice(Y)] for w in W], block)
+        for k in (0, nrhs - 1):
+            terr.append(rel_err(yr[k][lex(Y)], mg.restrict(P, host(vs[k][gslice(Y)]), block)[0]))
+            perr.append(rel_err(host(pv[k][gslice(Y)]),
+                                mg.prolong(P, ylex[k][lex(Y)][None, :].astype(np.complex128), block, block)))
+    print("restriction %.2e, prolongation %.2e" % (max(terr), max(perr)), flush=True)
+    assert max(terr) < 2e-6 and max(perr) < 2e-6, (terr, perr)
 
 
 def test_full_size_sap_and_restrict_sampled():
