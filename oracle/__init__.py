@@ -10,11 +10,6 @@ product path.
 
 All arithmetic is complex128.  Fields use the canonical layout documented in
 ``synth.fields``.  Pins tying every function to something other than itself
-live in ``tests/test_oracle_*.py``.  Functions whose exact values have no such
-pin say "parity unpinned" in their docstrings:
-
-* ``clover.clover_term`` -- sign and normalisation of the clover term: the
-  paper gives no formula or printed values (structure is pinned:
-  Hermitian 6x6 blocks, commutes with Gamma5, vanishes at U=1, linear in
-  c_sw, gauge covariant).
+live in ``tests/test_oracle_*.py``; a function whose exact values had no such
+pin would say "parity unpinned" in its docstring (none does).
 """

@@ -176,6 +176,55 @@ def test_clover_abelian_flux():
     assert np.abs(C - ref).max() < 1e-14
 
 
+def _uniform_flux_links(L0, L1, n):
+    """SU(3) links on L0 x L1 x 1 x 1 carrying n quanta of uniform abelian flux in the (0,1)
+    plane, colour-diagonal diag(B, -B, 0): every (0,1) plaquette equals exp(i B lambda),
+    B = 2 pi n / (L0 L1) (the twist on the last t-slice closes the torus)."""
+    dims = (L0, L1, 1, 1)
+    B = 2 * np.pi * n / (L0 * L1)
+    lam = np.array([1.0, -1.0, 0.0])
+    U = unit_links(dims)
+    for t in range(L0):
+        U[t, :, :, :, 1] = np.diag(np.exp(1j * B * t * lam))
+    for y in range(L1):
+        U[L0 - 1, y, :, :, 0] = np.diag(np.exp(-1j * B * L0 * y * lam))
+    return U, B
+
+
+def test_clover_tree_level_improvement():
+    """Sign and normalisation of the clover term, from the property the paper gives it
+    (Sec. 2, text after eq. (2.5); Sec. 4): it lowers the discretisation error from O(a)
+    to O(a^2).  In a uniform field B the lowest Landau level is annihilated by the
+    continuum gamma.D; expanding the Wilson term, -(1/2) Laplacian = -(1/2)(gamma.D)^2
+    - (i/4) sigma_{mu nu} F_{mu nu}, shifts those modes by the O(a) Pauli term +|B|/2, and
+    the clover term at c_sw = 1 cancels it.  So the near-zero eigenvalues of D (m0 = 0) are
+    (1 - c_sw) |B| / 2 + O(B^2), for either colour of the field; at c_sw = 1 what is left
+    falls as B^2 (4x smaller B, ~16x smaller eigenvalue), at c_sw = 0 only as B.  A flipped
+    sign, another normalisation of Fhat or sigma, or clockwise leaves move them by O(B)."""
+    left = {}
+    for L in (8, 16):
+        U, B = _uniform_flux_links(L, L, 1)
+        V = L * L
+        for csw in (0.0, 1.0, -1.0, 2.0):
+            A = dense.sparse_D(U, 0.0, clover.clover_term(U, csw) if csw else None)
+            for col in (0, 1):
+                idx = np.array([12 * i + 3 * s + col for i in range(V) for s in range(4)])
+                w = np.linalg.eigvals(A[idx][:, idx].toarray())
+                w = w[np.argsort(np.abs(w))]
+                # a degenerate real pair (the two spin states of the lowest level) ...
+                assert np.abs(w[:2].imag).max() < 1e-9
+                assert abs(w[0].real - w[1].real) < 1e-9
+                # ... well separated from the next level (|lambda| ~ sqrt(2 B))
+                assert np.abs(w[2]) > 4 * B
+                assert abs(w[0].real - (1 - csw) * B / 2) < 0.1 * B * B, (L, csw, col, w[0])
+                left[(L, csw, col)] = w[0].real
+    for col in (0, 1):
+        r1 = left[(8, 1.0, col)] / left[(16, 1.0, col)]
+        r0 = left[(8, 0.0, col)] / left[(16, 0.0, col)]
+        assert 12 < r1 < 20, r1
+        assert 3.5 < r0 < 4.5, r0
+
+
 def test_norm_bound_lambda_max():
     """|lambda| <= |m0 + 4| + 4 (+ ||C||); the paper's estimate lambda_max = 8 (Sec. 4)."""
     with open(GOLDEN) as f:
