@@ -3,6 +3,8 @@
 // A batch is nrhs vectors of n complex numbers, vector k at offset k*stride;
 // a basis V_j (j < J) is at offset j*vstride.  Dot products accumulate in
 // double whatever the storage precision.
+#include <type_traits>
+
 #include "qmg_ctx.h"
 #include "reduce.h"
 
@@ -60,11 +62,13 @@ __global__ __launch_bounds__(kDotWG) void k_dot_stage1(double* partial, const ty
   }
 }
 
-// w_k += sum_j coef[k*J+j] V_j,k over one chunk, and partial[k][chunk] = ||new w_k||^2 there
-template <typename S>
+// w_k += sum_j coef[k*J+j] V_j,k over one chunk, and partial[k][chunk] = ||new w_k||^2 there.
+// With a copy type C (FP32 or BF16 storage), the new w is also written to cp in
+// that storage, rounded through FP32 exactly as the conversion kernel rounds it.
+template <typename S, typename C = void>
 __global__ __launch_bounds__(kDotWG) void k_axpy_norm(typename PT<S>::stor* w, const typename PT<S>::stor* V,
                                                      int64_t vstride, int J, const double* coef, int64_t n,
-                                                     int64_t stride, int nchunk, double* partial) {
+                                                     int64_t stride, int nchunk, double* partial, C* cp) {
   using R = typename PT<S>::real;
   __shared__ double red[2 * (kDotWG / 64)];
   const int chunk = blockIdx.x, k = blockIdx.y;
@@ -82,6 +86,7 @@ __global__ __launch_bounds__(kDotWG) void k_axpy_norm(typename PT<S>::stor* w, c
       }
       const cpx<R> vr = {R(v.re), R(v.im)};
       stcv(wk, i, vr);
+      if constexpr (!std::is_void<C>::value) stcv(cp + k * stride, i, cpx<float>{float(vr.re), float(vr.im)});
       acc[0] += norm2(ldcv<double>(wk, i));
     }
   }
@@ -217,14 +222,25 @@ hipError_t launch_multidot_shared(int p, double* dots, const void* V, int64_t vs
 
 // w_k += sum_j coef V_j,k; norms[2k] = ||w_k||^2 afterwards (fixed summation order)
 hipError_t launch_axpy_norm(int p, void* w, const void* V, int64_t vstride, int J, const double* coef, int64_t n,
-                            int64_t stride, int nrhs, double* norms, double* partial, hipStream_t s) {
+                            int64_t stride, int nrhs, double* norms, double* partial, hipStream_t s, void* copy,
+                            int copy_prec) {
   const int nchunk = (int)((n + kChunk - 1) / kChunk);
-  by_prec(p, [&](auto tag) {
-    using S = decltype(tag);
-    using P = typename PT<S>::stor;
-    hipLaunchKernelGGL(k_axpy_norm<S>, dim3(nchunk, nrhs), dim3(kDotWG), 0, s, (P*)w, (const P*)V, vstride, J, coef,
-                       n, stride, nchunk, partial);
-  });
+  const dim3 grid(nchunk, nrhs), blk(kDotWG);
+  if (copy && p == QMG_F64 && copy_prec == QMG_F32) {
+    hipLaunchKernelGGL((k_axpy_norm<double, float2>), grid, blk, 0, s, (double2*)w, (const double2*)V, vstride, J,
+                       coef, n, stride, nchunk, partial, (float2*)copy);
+  } else if (copy && p == QMG_F64 && copy_prec == QMG_BF16) {
+    hipLaunchKernelGGL((k_axpy_norm<double, uint32_t>), grid, blk, 0, s, (double2*)w, (const double2*)V, vstride, J,
+                       coef, n, stride, nchunk, partial, (uint32_t*)copy);
+  } else {
+    if (copy) return hipErrorInvalidValue;  // only FP64 vectors are copied to FP32 / BF16
+    by_prec(p, [&](auto tag) {
+      using S = decltype(tag);
+      using P = typename PT<S>::stor;
+      hipLaunchKernelGGL((k_axpy_norm<S, void>), grid, blk, 0, s, (P*)w, (const P*)V, vstride, J, coef, n, stride,
+                         nchunk, partial, (void*)nullptr);
+    });
+  }
   hipLaunchKernelGGL(k_dot_stage2, dim3(1, nrhs), dim3(256), 0, s, norms, partial, 1, nchunk);
   return hipGetLastError();
 }

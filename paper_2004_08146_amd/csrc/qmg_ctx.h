@@ -150,9 +150,12 @@ qmg_status solver_setup_l3(qmg_ctx* c, void* W2, int ntv2, const int block2[4], 
 // dots[k*J + j] = <V_j,k , w_k> for j < J (V_j at base + j*vstride), FP64 results on device
 hipError_t launch_multidot(int p, double* dots, const void* V, int64_t vstride, int J, const void* w,
                            int64_t n, int64_t stride, int nrhs, double* partial, hipStream_t s, int with_self = 0);
-// w_k += sum_j coef[k*J + j] V_j,k and norms[2k] = ||w_k||^2 of the result
+// w_k += sum_j coef[k*J + j] V_j,k and norms[2k] = ||w_k||^2 of the result; with copy
+// (p == QMG_F64 only) the result is also written there in copy_prec (FP32 or BF16),
+// bit for bit what launch_convert would write
 hipError_t launch_axpy_norm(int p, void* w, const void* V, int64_t vstride, int J, const double* coef, int64_t n,
-                            int64_t stride, int nrhs, double* norms, double* partial, hipStream_t s);
+                            int64_t stride, int nrhs, double* norms, double* partial, hipStream_t s,
+                            void* copy = nullptr, int copy_prec = QMG_F64);
 // w_k += sum_j coef[k*J + j] * V_j,k   (coef complex double on device)
 hipError_t launch_multiaxpy(int p, void* w, const void* V, int64_t vstride, int J, const double* coef,
                             int64_t n, int64_t stride, int nrhs, hipStream_t s);
@@ -191,9 +194,11 @@ qmg_status level2_kcycle(qmg_ctx* c, int p, void* y, const void* r, const double
                          int s2, hipStream_t s, int qform = 0);
 // y += x for nrhs fields (n complex each, stride between fields)
 hipError_t launch_add(int p, void* y, const void* x, int64_t n, int64_t stride, int nrhs, hipStream_t s);
-// z = M r; z is written in precision zprec (FP64, or the preconditioner's own precision)
+// z = M r; z is written in precision zprec (FP64, or the preconditioner's own precision);
+// r is read in precision rprec (FP64, or the preconditioner's own precision)
 qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs,
-                         const qmg_params* prm, int* coarse_iters, hipStream_t s, int zprec = QMG_F64);
+                         const qmg_params* prm, int* coarse_iters, hipStream_t s, int zprec = QMG_F64,
+                         int rprec = QMG_F64);
 qmg_status solver_eigensolve(qmg_ctx* c, int nev, double* lambda, void* X, const void* V0, int n0,
                              const void* t0, const qmg_eig_params* prm, qmg_eig_stats* stats, hipStream_t s);
 void herm_eig(int m, std::vector<std::complex<double>> a, std::vector<double>& w,

@@ -152,9 +152,11 @@ struct Space {
   // (<= 20 eps here); the true residual is recomputed after every restart
   // cycle anyway.  The new norm comes out of the update pass.
   // sig (optional, [nrhs][j + 1]): the basis is stored unnormalised, v_i = sig_i W_i,
-  // so the projections use sig_i (W_i^H w) and the update subtracts sig_i^2 (W_i^H w) W_i
+  // so the projections use sig_i (W_i^H w) and the update subtracts sig_i^2 (W_i^H w) W_i.
+  // copy (optional): the update pass also writes the new w there in copy_prec.
   qmg_status arnoldi(std::vector<std::vector<cd>>& h, void* V, int j, void* w,
-                     const std::vector<std::vector<double>>* sig = nullptr) {
+                     const std::vector<std::vector<double>>* sig = nullptr, void* copy = nullptr,
+                     int copy_prec = QMG_F64) {
     const int J = j + 1;
     h.assign(nrhs, std::vector<cd>(j + 2, cd(0)));
     double* d = (double*)ws_get(c, "sp_dots", sizeof(double) * 2 * (J + 1) * nrhs);
@@ -181,7 +183,7 @@ struct Space {
         if (self) before[k] = hd[2 * ((size_t)k * (J + 1) + J)];
       }
       e = hipMemcpyAsync(dc, hc, sizeof(double) * 2 * J * nrhs, hipMemcpyHostToDevice, s);
-      if (e == hipSuccess) e = launch_axpy_norm(p, w, V, vstride(), J, dc, n, n, nrhs, d, part, s);
+      if (e == hipSuccess) e = launch_axpy_norm(p, w, V, vstride(), J, dc, n, n, nrhs, d, part, s, copy, copy_prec);
       if (e == hipSuccess) e = hipMemcpyAsync(hd, d, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) return hip_err(c, e, "Arnoldi update");
@@ -270,18 +272,19 @@ qmg_status solver_coarse_gmres(qmg_ctx* c, int p, void* y, const void* r, const 
 // graph_safe: the coarse GMRES runs a fixed number of steps with its scalars on
 // the device, so the whole V-cycle is a pure kernel sequence (no host sync).
 static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
-                              int* coarse_iters, hipStream_t s, bool graph_safe, int zprec);
+                              int* coarse_iters, hipStream_t s, bool graph_safe, int zprec, int rprec);
 
 qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
-                         int* coarse_iters, hipStream_t s, int zprec) {
+                         int* coarse_iters, hipStream_t s, int zprec, int rprec) {
   if (zprec != QMG_F64 && zprec != prm->mg_prec) return set_err(c, QMG_E_ARG, "V-cycle output precision");
-  if (!prm->use_graph) return vcycle_body(c, z, r, tau, nrhs, prm, coarse_iters, s, false, zprec);
+  if (rprec != QMG_F64 && rprec != prm->mg_prec) return set_err(c, QMG_E_ARG, "V-cycle input precision");
+  if (!prm->use_graph) return vcycle_body(c, z, r, tau, nrhs, prm, coarse_iters, s, false, zprec, rprec);
   // HIP-graph mode: capture the V-cycle once per (buffers, shifts, parameters) and replay it
   std::string key;
   {
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|", z, r, nrhs, prm->nu_post,
-                  prm->n_mr, prm->coarse_maxiter, (int)prm->mg_prec, prm->use_coarse, zprec, prm->q_form,
+    std::snprintf(buf, sizeof(buf), "%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|", z, r, nrhs, prm->nu_post,
+                  prm->n_mr, prm->coarse_maxiter, (int)prm->mg_prec, prm->use_coarse, zprec, rprec, prm->q_form,
                   prm->smoother, prm->levels, prm->l3_iters, prm->l2_smooth);
     key = buf;
     for (int k = 0; k < nrhs; ++k) {
@@ -299,7 +302,7 @@ qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, 
   // workspace buffer), then record the same sequence on the library's own
   // stream (the caller's stream may be the legacy default stream, which
   // cannot be captured); the recorded graph is later launched on `s`.
-  qmg_status st = vcycle_body(c, z, r, tau, nrhs, prm, nullptr, s, true, zprec);
+  qmg_status st = vcycle_body(c, z, r, tau, nrhs, prm, nullptr, s, true, zprec, rprec);
   if (st != QMG_OK) return st;
   hipError_t e = hipSuccess;
   if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
@@ -309,7 +312,7 @@ qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, 
   hipGraph_t graph = nullptr;
   e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_err(c, e, "begin capture");
-  st = vcycle_body(c, z, r, tau, nrhs, prm, nullptr, c->cap_stream, true, zprec);
+  st = vcycle_body(c, z, r, tau, nrhs, prm, nullptr, c->cap_stream, true, zprec, rprec);
   e = hipStreamEndCapture(c->cap_stream, &graph);
   if (st != QMG_OK) {
     if (graph) hipGraphDestroy(graph);
@@ -329,19 +332,23 @@ qmg_status solver_vcycle(qmg_ctx* c, void* z, const void* r, const double* tau, 
 }
 
 static qmg_status vcycle_body(qmg_ctx* c, void* z, const void* r, const double* tau, int nrhs, const qmg_params* prm,
-                              int* coarse_iters, hipStream_t s, bool graph_safe, int zprec) {
+                              int* coarse_iters, hipStream_t s, bool graph_safe, int zprec, int rprec) {
   const int p = prm->mg_prec;
   const int64_t n = (int64_t)field_elems(c);
   void* rp = (void*)r;
   void* zp = z;
   hipError_t e;
   if (p != QMG_F64) {
-    rp = ws_get(c, "vc_r", (size_t)n * nrhs * cbytes(p));
+    // an input already in the preconditioner's precision is read in place (the
+    // V-cycle only reads r)
+    if (rprec != p) rp = ws_get(c, "vc_r", (size_t)n * nrhs * cbytes(p));
     // with zprec == p the result is written straight into z
     if (zprec != p) zp = ws_get(c, "vc_z", (size_t)n * nrhs * cbytes(p));
     if (!rp || !zp) return set_err(c, QMG_E_NOMEM, "out of device memory (V-cycle)");
-    e = launch_convert(rp, p, r, QMG_F64, n * nrhs, s);
-    if (e != hipSuccess) return hip_err(c, e, "convert");
+    if (rprec != p) {
+      e = launch_convert(rp, p, r, QMG_F64, n * nrhs, s);
+      if (e != hipSuccess) return hip_err(c, e, "convert");
+    }
   }
   if (prm->use_coarse && c->have_mg) {
     const int cp = coarse_prec(p);
@@ -421,7 +428,12 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
   void* Z = ws_get(c, "fg_Z", zb_full * m);
   void* f = ws_get(c, "fg_f", bb);
   void* r = ws_get(c, "fg_r", bb);
-  if (!V || !Z || !f || !r) return set_err(c, QMG_E_NOMEM, "out of device memory (FGMRES)");
+  // a reduced-precision V-cycle reads its input in its own precision: the
+  // Gram-Schmidt update writes that copy of the next basis vector as it writes
+  // the FP64 one, which saves the V-cycle a conversion pass over the FP64 vector
+  const bool vin = prm->mg_prec != QMG_F64;
+  void* vc_in = vin ? ws_get(c, "fg_vin", zb_full) : nullptr;
+  if (!V || !Z || !f || !r || (vin && !vc_in)) return set_err(c, QMG_E_NOMEM, "out of device memory (FGMRES)");
   // Gamma5-preconditioned form: (D - tau Gamma5) x = Gamma5 b; q_form: (Q - tau) x = b itself
   const int mode = prm->q_form ? 1 : 0;
   hipError_t e = prm->q_form ? hipMemcpyAsync(f, b, bb, hipMemcpyDeviceToDevice, s)
@@ -533,6 +545,10 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
     }
     st = sp.scale(sp.at(V, 0), rw, a);
     if (st != QMG_OK) return st;
+    if (vin) {
+      e = launch_convert(vc_in, zprec, sp.at(V, 0), QMG_F64, n * na, s);
+      if (e != hipSuccess) return hip_err(c, e, "convert");
+    }
     // basis vectors after the first stay unnormalised (v_j = sig_j W_j): the
     // product A z_j is orthogonalised in place in the next basis slot, and the
     // preconditioner takes W_j itself (flexible GMRES allows any z_j)
@@ -544,14 +560,16 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
       void* w = sp.at(V, jj + 1);
       e = mark();
       if (e != hipSuccess) return hip_err(c, e, "event");
-      st = solver_vcycle(c, zat(jj), sp.at(V, jj), tw.data(), na, prm, &ci, s, zprec);
+      st = vin ? solver_vcycle(c, zat(jj), vc_in, tw.data(), na, prm, &ci, s, zprec, zprec)
+               : solver_vcycle(c, zat(jj), sp.at(V, jj), tw.data(), na, prm, &ci, s, zprec);
       if (st != QMG_OK) return st;
       e = mark();
       if (e == hipSuccess) e = launch_dslash_d_in(c, w, zat(jj), zprec, tw.data(), na, s, mode);
       if (e == hipSuccess) e = mark();
       if (e != hipSuccess) return hip_err(c, e, "apply");
       std::vector<std::vector<cd>> h;
-      st = sp.arnoldi(h, V, jj, w, &sig);
+      // the last step of a cycle has no next V-cycle
+      st = sp.arnoldi(h, V, jj, w, &sig, vin && jj + 1 < m ? vc_in : nullptr, zprec);
       if (st != QMG_OK) return st;
       e = mark();
       if (e != hipSuccess) return hip_err(c, e, "event");
