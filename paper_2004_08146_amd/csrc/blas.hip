@@ -132,16 +132,20 @@ __global__ __launch_bounds__(256) void k_multiaxpy(typename PT<S>::stor* w, cons
   }
 }
 
-template <typename S>
+// y_k = a_k x_k; with a copy type C (FP32 or BF16 storage) the result is also
+// written to cp, rounded through FP32 as the conversion kernel rounds it
+template <typename S, typename C = void>
 __global__ __launch_bounds__(256) void k_scale(typename PT<S>::stor* y, const typename PT<S>::stor* x, const double* a,
-                                               int64_t n, int64_t stride) {
+                                               int64_t n, int64_t stride, C* cp) {
   using R = typename PT<S>::real;
   const int k = blockIdx.y;
   const cpx<double> ak = {a[2 * k], a[2 * k + 1]};
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
     cpx<double> v = ak * ldcv<double>(x + k * stride, i);
-    stcv(y + k * stride, i, cpx<R>{R(v.re), R(v.im)});
+    const cpx<R> vr = {R(v.re), R(v.im)};
+    stcv(y + k * stride, i, vr);
+    if constexpr (!std::is_void<C>::value) stcv(cp + k * stride, i, cpx<float>{float(vr.re), float(vr.im)});
   }
 }
 
@@ -273,12 +277,22 @@ hipError_t launch_multiaxpy_d(void* w, const void* V, int vprec, int64_t vstride
 }
 
 hipError_t launch_scale(int p, void* y, const void* x, const double* a, int64_t n, int64_t stride, int nrhs,
-                        hipStream_t s) {
-  by_prec(p, [&](auto tag) {
-    using S = decltype(tag);
-    using P = typename PT<S>::stor;
-    hipLaunchKernelGGL(k_scale<S>, dim3(ew_grid(n), nrhs), dim3(256), 0, s, (P*)y, (const P*)x, a, n, stride);
-  });
+                        hipStream_t s, void* copy, int copy_prec) {
+  const dim3 grid(ew_grid(n), nrhs), blk(256);
+  if (copy && p == QMG_F64 && copy_prec == QMG_F32) {
+    hipLaunchKernelGGL((k_scale<double, float2>), grid, blk, 0, s, (double2*)y, (const double2*)x, a, n, stride,
+                       (float2*)copy);
+  } else if (copy && p == QMG_F64 && copy_prec == QMG_BF16) {
+    hipLaunchKernelGGL((k_scale<double, uint32_t>), grid, blk, 0, s, (double2*)y, (const double2*)x, a, n, stride,
+                       (uint32_t*)copy);
+  } else {
+    if (copy) return hipErrorInvalidValue;  // only FP64 vectors are copied to FP32 / BF16
+    by_prec(p, [&](auto tag) {
+      using S = decltype(tag);
+      using P = typename PT<S>::stor;
+      hipLaunchKernelGGL((k_scale<S, void>), grid, blk, 0, s, (P*)y, (const P*)x, a, n, stride, (void*)nullptr);
+    });
+  }
   return hipGetLastError();
 }
 

@@ -162,9 +162,10 @@ hipError_t launch_multiaxpy(int p, void* w, const void* V, int64_t vstride, int 
 // as launch_multiaxpy with w in FP64 and the J vectors V stored in vprec
 hipError_t launch_multiaxpy_d(void* w, const void* V, int vprec, int64_t vstride, int J, const double* coef,
                               int64_t n, int64_t stride, int nrhs, hipStream_t s);
-// y_k = a_k * x_k (a complex double on device, may alias)
+// y_k = a_k * x_k (a complex double on device, may alias); with copy (p == QMG_F64
+// only) the result is also written there in copy_prec, as launch_convert would write it
 hipError_t launch_scale(int p, void* y, const void* x, const double* a, int64_t n, int64_t stride,
-                        int nrhs, hipStream_t s);
+                        int nrhs, hipStream_t s, void* copy = nullptr, int copy_prec = QMG_F64);
 // y_k = x_k - y_k  (xmy) or y_k = y_k + x_k
 hipError_t launch_xmy(int p, void* y, const void* x, int64_t n, int64_t stride, int nrhs, hipStream_t s);
 hipError_t launch_gamma5_bs(int p, void* y, const void* x, int64_t n, int bs_log, hipStream_t s);

@@ -134,13 +134,13 @@ struct Space {
     if (e != hipSuccess) return hip_err(c, e, "axpy");
     return QMG_OK;
   }
-  qmg_status scale(void* y, const void* x, const std::vector<cd>& a) {
+  qmg_status scale(void* y, const void* x, const std::vector<cd>& a, void* copy = nullptr, int copy_prec = QMG_F64) {
     double* d = (double*)ws_get(c, "sp_scale", sizeof(double) * 2 * nrhs);
     if (!d) return set_err(c, QMG_E_NOMEM, "out of device memory (scale)");
     double* h = host_buf(c, "scale", 2 * nrhs);
     for (int k = 0; k < nrhs; ++k) { h[2 * k] = a[k].real(); h[2 * k + 1] = a[k].imag(); }
     hipError_t e = hipMemcpyAsync(d, h, sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_scale(p, y, x, d, n, n, nrhs, s);
+    if (e == hipSuccess) e = launch_scale(p, y, x, d, n, n, nrhs, s, copy, copy_prec);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_err(c, e, "scale");
     return QMG_OK;
@@ -543,12 +543,9 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
       lsq[i].init(m, rnorm[cols[i]]);
       if (act[i]) restarts[cols[i]] += 1;
     }
-    st = sp.scale(sp.at(V, 0), rw, a);
+    // the first basis vector, and the V-cycle's reduced-precision copy of it
+    st = sp.scale(sp.at(V, 0), rw, a, vc_in, zprec);
     if (st != QMG_OK) return st;
-    if (vin) {
-      e = launch_convert(vc_in, zprec, sp.at(V, 0), QMG_F64, n * na, s);
-      if (e != hipSuccess) return hip_err(c, e, "convert");
-    }
     // basis vectors after the first stay unnormalised (v_j = sig_j W_j): the
     // product A z_j is orthogonalised in place in the next basis slot, and the
     // preconditioner takes W_j itself (flexible GMRES allows any z_j)
