@@ -200,6 +200,38 @@ struct Space {
     for (int k = 0; k < nrhs; ++k) h[k][j + 1] = std::sqrt(std::max(0.0, after[k]));
     return QMG_OK;
   }
+  // The last Arnoldi step of a restart cycle. Its new vector is never used (the
+  // next cycle starts from the true residual), so only the projections h and
+  // the norm of the projected part are formed: one pass gives W_i^H w and
+  // ||w||^2, and ||w - sum_i h_i v_i||^2 = ||w||^2 - sum_i |h_i|^2 with the v_i
+  // orthonormal. The subtraction loses about eps ||w||^2 / ||w_new||^2 in
+  // relative accuracy, which only perturbs this cycle's last rotation.
+  qmg_status arnoldi_last(std::vector<std::vector<cd>>& h, void* V, int j, void* w,
+                          const std::vector<std::vector<double>>* sig = nullptr) {
+    const int J = j + 1;
+    h.assign(nrhs, std::vector<cd>(j + 2, cd(0)));
+    double* d = (double*)ws_get(c, "sp_dots", sizeof(double) * 2 * (J + 1) * nrhs);
+    double* part = (double*)ws_get(c, "sp_part", sizeof(double) * multidot_partial_doubles(n, J + 1, nrhs));
+    if (!d || !part) return set_err(c, QMG_E_NOMEM, "out of device memory (Arnoldi)");
+    double* hd = host_buf(c, "dots", 2 * (J + 1) * nrhs);
+    hipError_t e = launch_multidot(p, d, V, vstride(), J, w, n, n, nrhs, part, s, 1);
+    if (e == hipSuccess) e = hipMemcpyAsync(hd, d, sizeof(double) * 2 * (J + 1) * nrhs, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(c, e, "Arnoldi dots");
+    for (int k = 0; k < nrhs; ++k) {
+      double proj = 0.0;
+      for (int i = 0; i < J; ++i) {
+        const double* q = hd + 2 * ((size_t)k * (J + 1) + i);
+        const double si = sig ? (*sig)[k][i] : 1.0;
+        h[k][i] = si * cd(q[0], q[1]);
+        proj += std::norm(h[k][i]);
+      }
+      const double ww = hd[2 * ((size_t)k * (J + 1) + J)];
+      if (!std::isfinite(ww) || !std::isfinite(proj)) return set_err(c, QMG_E_NUMERIC, "non-finite norm in Arnoldi step");
+      h[k][j + 1] = std::sqrt(std::max(0.0, ww - proj));
+    }
+    return QMG_OK;
+  }
 };
 
 }  // namespace
@@ -565,8 +597,12 @@ qmg_status solver_fgmres(qmg_ctx* c, void* x, const void* b, const double* tau, 
       if (e == hipSuccess) e = mark();
       if (e != hipSuccess) return hip_err(c, e, "apply");
       std::vector<std::vector<cd>> h;
-      // the last step of a cycle has no next V-cycle
-      st = sp.arnoldi(h, V, jj, w, &sig, vin && jj + 1 < m ? vc_in : nullptr, zprec);
+      // the last step of a restart cycle that another cycle follows keeps no new
+      // basis vector (and has no next V-cycle); a step at which maxiter ends the
+      // solve keeps the full update, so short inner solves (the eigensolver's
+      // correction equations) are unchanged by this shortcut
+      const bool last = jj + 1 == m && total + 1 < prm->maxiter;
+      st = last ? sp.arnoldi_last(h, V, jj, w, &sig) : sp.arnoldi(h, V, jj, w, &sig, vin ? vc_in : nullptr, zprec);
       if (st != QMG_OK) return st;
       e = mark();
       if (e != hipSuccess) return hip_err(c, e, "event");
