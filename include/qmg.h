@@ -228,8 +228,9 @@ qmg_status qmg_vcycle(qmg_ctx* ctx, void* z, const void* r, const double* tau, i
                       const qmg_params* params, hipStream_t stream);
 
 /* Solve (Q - tau_k I) x_k = b_k for k < nrhs (internal F64 fields x, b) by
- * FGMRES on (D - tau_k Gamma5) x_k = Gamma5 b_k, x0 = 0, each right-hand side
- * with its own Krylov space; stats: host array of nrhs (may be NULL).
+ * FGMRES on (D - tau_k Gamma5) x_k = Gamma5 b_k, from x = 0 (or from the
+ * caller's x when params->x0 = 1), each right-hand side with its own Krylov
+ * space; stats: host array of nrhs (may be NULL).
  * Columns that have converged when a restart cycle ends leave the batch (when
  * at most three quarters remain): later cycles run on the others only, in
  * library buffers, and every column's x is written back to its own slot.
