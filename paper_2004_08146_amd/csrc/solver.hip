@@ -5,11 +5,13 @@
 // Outer method: right-preconditioned flexible GMRES (Sec. 2 names FGMRES with
 // a multigrid preconditioner) on the Gamma5-preconditioned system
 // (D - tau Gamma5) x = Gamma5 b (eq. (3.6) <=> eq. (3.7)).  Arnoldi uses
-// classical Gram-Schmidt applied twice (CGS2) with batched dot products; the
-// small least-squares problems are solved on the host with complex Givens
-// rotations.  Each right-hand side runs its own Krylov space; the batch
-// advances in lock step and finished columns are frozen (their basis vectors
-// are zero, so every kernel still sees a fixed batch shape).
+// batched classical Gram-Schmidt with a second pass when the projection
+// cancels most of the vector (DGKS test); the small least-squares problems are
+// solved on the host with complex Givens rotations.  Each right-hand side runs
+// its own Krylov space; the batch advances in lock step within a restart
+// cycle (a column that converges inside a cycle keeps being orthogonalised,
+// its coefficients unused), and columns that have converged when a cycle ends
+// leave the batch.
 #include <chrono>
 #include <cmath>
 #include <complex>
