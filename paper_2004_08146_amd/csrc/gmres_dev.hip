@@ -4,7 +4,12 @@
 // The same driver runs the GMRES smoother on the fine level and, with a third
 // level, the level-3 GMRES and the level-2 flexible GMRES (K-cycle).
 // Being part of the preconditioner, this coarse GMRES makes a single classical
-// Gram-Schmidt pass per step (no data-dependent second pass).
+// Gram-Schmidt pass per step (no data-dependent second pass).  The basis is
+// stored unnormalised after its first vector (v_j = sig_j W_j, W_j the stored
+// vector): each product is orthogonalised in place in the next basis slot, so
+// no scaling pass is needed, and the last step, whose new vector is never used,
+// takes ||w_new||^2 = ||w||^2 - sum_i |v_i^H w|^2 from its dot pass instead of
+// an update pass.
 // One thread per right-hand side; the rotations follow the same convention as
 // the host solver: [[c, s], [-conj(s), c]] [a; b] = [r; 0], c real.
 #include <functional>
@@ -20,6 +25,7 @@ struct GmState {
   double* cs;    // [nrhs][m]
   double* sn;    // [nrhs][m] complex
   double* beta;  // [nrhs]
+  double* sig;   // [nrhs][m+1]: v_j = sig_j W_j
   int m;
 };
 
@@ -37,23 +43,37 @@ __global__ void k_gm_init(GmState st, const double* norms, double* a, int nrhs) 
   const int m = st.m;
   for (int i = 0; i <= m; ++i) stz(st.g, (int64_t)k * (m + 1) + i, cpx<double>{i == 0 ? b : 0.0, 0.0});
   for (int i = 0; i < (m + 1) * m; ++i) stz(st.H, (int64_t)k * (m + 1) * m + i, czero<double>());
+  for (int i = 0; i <= m; ++i) st.sig[(int64_t)k * (m + 1) + i] = i == 0 ? 1.0 : 0.0;
 }
 
-// one classical Gram-Schmidt pass: H[:, j] += dots, coef = -dots
-__global__ void k_gm_coef(GmState st, const double* dots, double* coef, int j, int nrhs) {
+// one classical Gram-Schmidt pass for w = A W_j, d_i = W_i^H w:
+// H[i][j] = sig_i sig_j d_i, coef_i = -sig_i^2 d_i (w -= (v_i^H w) v_i).
+// last: dots also holds ||w||^2 (at index J), and norms[2k] gets the squared
+// norm of the projected w, ||w||^2 - sum_i sig_i^2 |d_i|^2, in place of the
+// update pass
+__global__ void k_gm_coef(GmState st, const double* dots, double* coef, int j, int nrhs, int last,
+                          double* norms) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nrhs) return;
-  const int J = j + 1, m = st.m;
+  const int J = j + 1, m = st.m, ld = J + (last ? 1 : 0);
+  const double* sg = st.sig + (int64_t)k * (m + 1);
+  double proj = 0.0;
   for (int i = 0; i < J; ++i) {
-    const cpx<double> d = ldz(dots, (int64_t)k * J + i);
+    const cpx<double> d = ldz(dots, (int64_t)k * ld + i);
     const int64_t hi = (int64_t)k * (m + 1) * m + (int64_t)i * m + j;
-    stz(st.H, hi, ldz(st.H, hi) + d);
-    stz(coef, (int64_t)k * J + i, -d);
+    stz(st.H, hi, ldz(st.H, hi) + (sg[i] * sg[j]) * d);
+    stz(coef, (int64_t)k * J + i, -(sg[i] * sg[i]) * d);
+    proj += sg[i] * sg[i] * norm2(d);
+  }
+  if (last) {
+    norms[2 * k] = fmax(dots[2 * ((int64_t)k * ld + J)] - proj, 0.0);
+    norms[2 * k + 1] = 0.0;
   }
 }
 
-// close column j: h_{j+1,j} = ||w||, rotate, update g, a = 1/h_{j+1,j}
-__global__ void k_gm_col(GmState st, const double* norms, double* a, int j, int nrhs) {
+// close column j: h_{j+1,j} = sig_j ||w_new|| (w_new = the projected A W_j,
+// stored as W_{j+1}, so sig_{j+1} = 1 / ||w_new||), rotate, update g
+__global__ void k_gm_col(GmState st, const double* norms, int j, int nrhs) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nrhs) return;
   const int m = st.m;
@@ -61,7 +81,10 @@ __global__ void k_gm_col(GmState st, const double* norms, double* a, int j, int 
   double* g = st.g + (int64_t)k * (m + 1) * 2;
   double* cs = st.cs + (int64_t)k * m;
   double* sn = st.sn + (int64_t)k * m * 2;
-  const double hn = sqrt(fmax(norms[2 * k], 0.0));
+  double* sg = st.sig + (int64_t)k * (m + 1);
+  const double wn = sqrt(fmax(norms[2 * k], 0.0));
+  const double hn = sg[j] * wn;
+  sg[j + 1] = wn > 0 ? 1.0 / wn : 0.0;
   cpx<double> h[2];
   for (int i = 0; i < j; ++i) {
     const cpx<double> hi = ldz(H, (int64_t)i * m + j), hi1 = ldz(H, (int64_t)(i + 1) * m + j);
@@ -88,8 +111,6 @@ __global__ void k_gm_col(GmState st, const double* norms, double* a, int j, int 
   const cpx<double> gj = ldz(g, j);
   stz(g, j + 1, -(conj(s) * gj));
   stz(g, j, c * gj);
-  a[2 * k] = hn > 0 ? 1.0 / hn : 0.0;
-  a[2 * k + 1] = 0.0;
 }
 
 // y = R^{-1} g (R: the rotated Hessenberg, kk columns) -> coef[k][0..kk)
@@ -108,6 +129,9 @@ __global__ void k_gm_solve(GmState st, double* coef, int kk, int nrhs) {
     stz(coef, (int64_t)k * kk + i, dd > 0 ? cpx<double>{(t.re * d.re + t.im * d.im) / dd, (t.im * d.re - t.re * d.im) / dd}
                                          : czero<double>());
   }
+  // y_i multiplies v_i = sig_i W_i (or M v_i = sig_i Z_i): coefficients of the stored vectors
+  const double* sg = st.sig + (int64_t)k * (m + 1);
+  for (int i = 0; i < kk; ++i) stz(coef, (int64_t)k * kk + i, sg[i] * ldz(coef, (int64_t)k * kk + i));
 }
 
 }  // namespace
@@ -136,7 +160,6 @@ static qmg_status gmres_device(qmg_ctx* c, const DevOp& op, void* y, const void*
   const std::string& tag = op.tag;
   const bool flex = (bool)op.prec;
   void* V = ws_get(c, tag + "_V", bb * (m + 1));
-  void* w = ws_get(c, tag + "_w", bb);
   void* Z = flex ? ws_get(c, tag + "_Z", bb * m) : nullptr;
   double* dots = (double*)ws_get(c, tag + "_dots", sizeof(double) * 2 * (m + 2) * nrhs);
   double* part = (double*)ws_get(c, tag + "_part", sizeof(double) * multidot_partial_doubles(n, m + 2, nrhs));
@@ -150,8 +173,9 @@ static qmg_status gmres_device(qmg_ctx* c, const DevOp& op, void* y, const void*
   st.cs = (double*)ws_get(c, tag + "_cs", sizeof(double) * m * nrhs);
   st.sn = (double*)ws_get(c, tag + "_sn", sizeof(double) * 2 * m * nrhs);
   st.beta = (double*)ws_get(c, tag + "_beta", sizeof(double) * nrhs);
-  if (!V || !w || (flex && !Z) || !dots || !part || !coef || !a || !nrm || !st.H || !st.g || !st.cs || !st.sn ||
-      !st.beta)
+  st.sig = (double*)ws_get(c, tag + "_sig", sizeof(double) * (m + 1) * nrhs);
+  if (!V || (flex && !Z) || !dots || !part || !coef || !a || !nrm || !st.H || !st.g || !st.cs || !st.sn ||
+      !st.beta || !st.sig)
     return set_err(c, QMG_E_NOMEM, "out of device memory (device GMRES)");
   const dim3 g1((nrhs + 63) / 64), b1(64);
   const int64_t vs = n * nrhs;
@@ -162,6 +186,8 @@ static qmg_status gmres_device(qmg_ctx* c, const DevOp& op, void* y, const void*
   }
   for (int j = 0; j < m && e == hipSuccess; ++j) {
     char* Vj = (char*)V + (size_t)j * bb;
+    char* w = Vj + bb;  // the product is orthogonalised in place in slot j + 1
+    const int last = j + 1 == m ? 1 : 0;
     if (flex) {
       char* Zj = (char*)Z + (size_t)j * bb;
       qmg_status ps = op.prec(Zj, Vj);
@@ -170,15 +196,12 @@ static qmg_status gmres_device(qmg_ctx* c, const DevOp& op, void* y, const void*
     } else {
       e = op.apply(w, Vj);
     }
-    if (e == hipSuccess) e = launch_multidot(cp, dots, V, vs, j + 1, w, n, n, nrhs, part, s, 0);
+    if (e == hipSuccess) e = launch_multidot(cp, dots, V, vs, j + 1, w, n, n, nrhs, part, s, last);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_gm_coef, g1, b1, 0, s, st, dots, coef, j, nrhs);
-      e = launch_axpy_norm(cp, w, V, vs, j + 1, coef, n, n, nrhs, nrm, part, s);
+      hipLaunchKernelGGL(k_gm_coef, g1, b1, 0, s, st, dots, coef, j, nrhs, last, nrm);
+      if (!last) e = launch_axpy_norm(cp, w, V, vs, j + 1, coef, n, n, nrhs, nrm, part, s);
     }
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_gm_col, g1, b1, 0, s, st, nrm, a, j, nrhs);
-      if (j + 1 < m) e = launch_scale(cp, (char*)V + (size_t)(j + 1) * bb, w, a, n, n, nrhs, s);
-    }
+    if (e == hipSuccess) hipLaunchKernelGGL(k_gm_col, g1, b1, 0, s, st, nrm, j, nrhs);
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_gm_solve, g1, b1, 0, s, st, coef, m, nrhs);
